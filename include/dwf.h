@@ -1,0 +1,201 @@
+/*
+ * dwf.h — C ABI of the MI355X domain-wall fermion operator library (libdwf.so).
+ *
+ * The library applies the 5D Shamir domain-wall Dirac operator, which the
+ * paper names as the kernel that dominates its run time and that it profiles
+ * against memory bandwidth (Introduction; Performance results, the profiler
+ * figures of the main DWF kernel; Conclusion, the node-local Wilson matrix).
+ * The paper does not write the operator down; the library implements the
+ * standard definitions, with these conventions:
+ *
+ *   sites x = (x0,x1,x2,x3), extents dims = {Lx,Ly,Lz,Lt}, all even;
+ *   lex(x) = x0 + Lx*(x1 + Ly*(x2 + Lz*x3)); parity(x) = (x0+x1+x2+x3) mod 2;
+ *   checkerboard row c(x) = lex(x) >> 1 (0 <= c < V/2);
+ *   gamma_mu = [[0, e_mu],[e_mu^dag, 0]] (chiral), e_0 = -i s1, e_1 = -i s2, e_2 = -i s3, e_3 = 1;
+ *   D_h psi(x,s) = sum_mu (1-gamma_mu) eta_mu(x) U_mu(x) psi(x+mu,s)
+ *                       + (1+gamma_mu) eta_mu(x-mu) U_mu(x-mu)^dag psi(x-mu,s),
+ *     eta_3(x) = -1 on links leaving t = Lt-1 when antiperiodic_t, else +1;
+ *     D_h^dag swaps (1-gamma) and (1+gamma);
+ *   M5op psi(s) = (5-M5) psi(s) - P_- psi~(s+1) - P_+ psi~(s-1), psi~ wraps with -mf,
+ *     P_+ keeps spins 0,1 and P_- spins 2,3;
+ *   D_DW = M5op - D_h/2;  M_pc = M5op - 1/4 D_h^{o<-e} M5op^-1 D_h^{e<-o} on the odd checkerboard.
+ *
+ * Canonical layouts (complex FP64, interleaved re,im, DEVICE memory owned by the caller):
+ *   gauge        [Lt][Lz][Ly][Lx][4][3][3]      (U[..][mu][a][b], link x -> x+mu)
+ *   full field   [Lt][Lz][Ly][Lx][Ls][4][3]
+ *   cb field     [V/2][Ls][4][3]                 (row c(x) of one parity)
+ *   force        [Lt][Lz][Ly][Lx][4][3][3]
+ * Internal fields (the `void*` field arguments) are in the library's private
+ * layout and precision; convert with dwf_pack / dwf_unpack, size them with
+ * dwf_field_bytes.  A full internal field is the even checkerboard followed by
+ * the odd one.  All pointers are device pointers unless marked host.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = legacy default stream).  Every
+ * call only enqueues work on it and returns, except dwf_cg, dwf_solve,
+ * dwf_norm2, dwf_cdot and dwf_tune, which synchronise that stream.
+ *
+ * Errors: every call returns a dwf_status; on failure dwf_last_error()
+ * returns a message for the calling thread.  No C++ exception crosses the ABI.
+ * A failed call leaves its outputs unspecified and the context usable.
+ *
+ * Allocation: dwf_create allocates the link copies and the operator
+ * temporaries; dwf_cg / dwf_solve allocate solver workspace on first use;
+ * dwf_batch_plan allocates its descriptor tables.  dwf_dhop, dwf_m5, dwf_mpc,
+ * dwf_mdagm, dwf_dw, dwf_axpy and dwf_force never allocate.
+ * A context may be used from one host thread at a time.
+ */
+#ifndef DWF_H
+#define DWF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dwf_ctx_s *dwf_ctx;
+typedef struct dwf_batch_s *dwf_batch;
+
+/* Storage precision of an internal field.  F16 and BF16 store spinors and
+ * links in 16 bits and compute in FP32. */
+typedef enum { DWF_F64 = 0, DWF_F32 = 1, DWF_F16 = 2, DWF_BF16 = 3 } dwf_prec;
+
+typedef enum {
+    DWF_OK = 0,
+    DWF_EINVAL = -1,  /* bad argument: odd/too small extents, Ls out of range, NULL pointer, bad enum */
+    DWF_ENOMEM = -2,  /* device allocation failed */
+    DWF_EHIP = -3,    /* a HIP runtime call failed; the message carries hipGetErrorString */
+    DWF_ENOCONV = -4, /* solver hit maxit before tol; stats are filled and x holds the last iterate */
+    DWF_ENAN = -5,    /* solver met a non-finite residual */
+    DWF_EUNSUP = -6,  /* valid but unsupported combination (e.g. gauge not set yet) */
+} dwf_status;
+
+typedef struct {
+    int dims[4];        /* Lx, Ly, Lz, Lt: even, >= 2 */
+    int Ls;             /* fifth-dimension extent, 1 <= Ls <= 64 */
+    double M5;          /* domain-wall height */
+    double mf;          /* quark mass on the s wraps */
+    int antiperiodic_t; /* 1: eta_3 = -1 on the time-boundary links */
+} dwf_geom;
+
+typedef struct {
+    int outer_iters;       /* defect-correction restarts (1 for plain FP64 CG) */
+    int inner_iters;       /* total CG iterations (all precisions) */
+    double true_rel_resid; /* ||b - A x|| / ||b|| in FP64 at exit */
+    double seconds;        /* host wall time of the call */
+} dwf_cg_stats;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Validates geom, binds the current HIP device, allocates link storage for
+ * all precisions and two FP64-sized checkerboard temporaries. */
+int dwf_create(const dwf_geom *geom, dwf_ctx *out);
+int dwf_destroy(dwf_ctx ctx);
+const char *dwf_last_error(void);
+
+/* Bytes of one internal checkerboard field (full = 0) or full 5D field (full = 1). */
+int dwf_field_bytes(dwf_ctx ctx, int prec, int full, size_t *bytes);
+
+/* Copies the canonical FP64 gauge field into the library's gathered link
+ * tables (8 links per checkerboard site, backward links stored daggered,
+ * eta folded in) in every precision.  U itself is not modified and may be
+ * freed afterwards.  Any complex 3x3 matrices are accepted (not only SU(3)). */
+int dwf_set_gauge(dwf_ctx ctx, const double *U, void *stream);
+
+/* Canonical FP64 <-> internal field of precision prec.
+ * parity 0 / 1: one checkerboard, canonical [V/2][Ls][4][3];
+ * parity 2:     full field, canonical [Lt][Lz][Ly][Lx][Ls][4][3]. */
+int dwf_pack(dwf_ctx ctx, void *internal, const double *canonical, int parity, int prec, void *stream);
+int dwf_unpack(dwf_ctx ctx, double *canonical, const void *internal, int parity, int prec, void *stream);
+
+/* Element-wise precision change of an internal field (round to nearest even). */
+int dwf_convert(dwf_ctx ctx, void *out, int out_prec, const void *in, int in_prec, int full, void *stream);
+
+/* ---- operators (checkerboard fields unless stated) ------------------------ */
+
+/* out = D_h^{p<-1-p} in (dagger = 0) or (D_h^dag)^{p<-1-p} in (dagger = 1),
+ * p = out_parity; the raw hopping term, no -1/2. in and out must not alias. */
+int dwf_dhop(dwf_ctx ctx, void *out, const void *in, int out_parity, int dagger, int prec, void *stream);
+
+/* out = M5op in, M5op^dag in, M5op^-1 in or M5op^-dag in (dagger, inverse in {0,1});
+ * full = 0: one checkerboard, full = 1: a full field.  in and out may alias. */
+int dwf_m5(dwf_ctx ctx, void *out, const void *in, int dagger, int inverse, int full, int prec, void *stream);
+
+/* out = M_pc in (dagger = 0) or M_pc^dag in (dagger = 1) on the odd checkerboard. */
+int dwf_mpc(dwf_ctx ctx, void *out, const void *in, int dagger, int prec, void *stream);
+
+/* out = M_pc^dag M_pc in on the odd checkerboard. */
+int dwf_mdagm(dwf_ctx ctx, void *out, const void *in, int prec, void *stream);
+
+/* out = D_DW in (dagger = 0) or D_DW^dag in (dagger = 1) on full fields. */
+int dwf_dw(dwf_ctx ctx, void *out, const void *in, int dagger, int prec, void *stream);
+
+/* ---- BLAS-1 and FP64 reductions (deterministic, fixed-order trees) -------- */
+
+/* *result (host) = sum |x|^2 accumulated in FP64. Synchronises the stream. */
+int dwf_norm2(dwf_ctx ctx, double *result, const void *x, int full, int prec, void *stream);
+/* result[0] + i result[1] (host) = <x, y> = sum conj(x) y in FP64. Synchronises. */
+int dwf_cdot(dwf_ctx ctx, double *result, const void *x, const void *y, int full, int prec, void *stream);
+/* y = (a_re + i a_im) x + y. */
+int dwf_axpy(dwf_ctx ctx, void *y, double a_re, double a_im, const void *x, int full, int prec, void *stream);
+
+/* ---- solvers -------------------------------------------------------------- */
+
+/* Solves M_pc^dag M_pc x = b on the odd checkerboard (FP64 internal fields),
+ * starting from the x passed in, until ||b - A x|| / ||b|| <= tol (recomputed in FP64).
+ * mode 0: FP64 CG.  mode 1/2/3: FP64 defect correction around inner CG whose
+ * operator stores spinors and links in FP32 / FP16 / BF16 (FP32 vectors,
+ * FP64 reductions).  maxit bounds the total CG iterations.  stats may be NULL. */
+int dwf_cg(dwf_ctx ctx, void *x, const void *b, double tol, int maxit, int mode, dwf_cg_stats *stats,
+           void *stream);
+
+/* Inner-solve controls of modes 1-3: relative residual target of each inner
+ * solve and its iteration cap (<= 0 restores the defaults 1e-5 / 1e-3 for
+ * FP32 / 16-bit and 2000). */
+int dwf_cg_set_inner(dwf_ctx ctx, double inner_tol, int inner_maxit);
+
+/* Solves D_DW x = b (dagger = 0) or D_DW^dag x = b (dagger = 1) on full FP64
+ * internal fields via the odd-checkerboard Schur complement and dwf_cg
+ * (x is overwritten; b is not modified). */
+int dwf_solve(dwf_ctx ctx, void *x, const void *b, int dagger, double tol, int maxit, int mode,
+              dwf_cg_stats *stats, void *stream);
+
+/* ---- fermion force ---------------------------------------------------------- */
+
+/* From full FP64 internal fields X, Y, writes canonical FP64 F (complex
+ * [V][4][3][3]):  M_mu(x) = sum_s tr_spin[(1-gamma_mu) X(x+mu,s) Y(x,s)^dag],
+ * N_mu(x) = sum_s tr_spin[(1+gamma_mu) X(x,s) Y(x+mu,s)^dag];
+ * kind 0: F = scale * eta (M^dag + N), the gradient of Re(Y^dag D_h X) with
+ *         respect to U in the convention delta f = Re sum conj(F) delta U;
+ * kind 1: F = scale * traceless part of (i/2)(G - G^dag), G = eta (U M - N U^dag),
+ *         the su(3) force: d/d(eps) Re(Y^dag D_h X) under U -> exp(i eps Q) U
+ *         equals sum tr(Q F) / scale.  kind 1 needs the gauge set. */
+int dwf_force(dwf_ctx ctx, double *F, const void *X, const void *Y, int kind, double scale, void *stream);
+
+/* ---- batched hopping term ---------------------------------------------------- */
+
+/* A plan applies dwf_dhop (same out_parity, dagger and precision) to nrhs[i]
+ * fields of each of nlat contexts (lattices may differ in volume and Ls) in
+ * one persistent launch.  The contexts must outlive the plan and have their
+ * gauge set.  dwf_batch_capture binds the field pointers (outs / ins list the
+ * fields lattice by lattice, sum(nrhs) each) and records the launch into a
+ * HIP graph on `stream`; dwf_batch_launch replays it. */
+int dwf_batch_plan(const dwf_ctx *ctxs, int nlat, const int *nrhs, int prec, int dagger, dwf_batch *plan);
+int dwf_batch_capture(dwf_batch plan, void *const *outs, const void *const *ins, int out_parity, void *stream);
+int dwf_batch_launch(dwf_batch plan, void *stream);
+int dwf_batch_free(dwf_batch plan);
+
+/* ---- autotuning --------------------------------------------------------------- */
+
+/* Times the launch shapes of the hopping kernel for (prec, dagger) on this
+ * context's lattice and keeps the fastest; the choice is cached in memory and,
+ * if the environment variable DWF_TUNE_CACHE names a file, on disk.  *best_us
+ * (host, may be NULL) receives the best time per apply.  Scratch fields are
+ * allocated and freed inside. Synchronises the stream. */
+int dwf_tune(dwf_ctx ctx, int prec, int dagger, double *best_us, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DWF_H */

@@ -1,0 +1,465 @@
+// The C ABI of libdwf.so: argument validation, context lifetime and the
+// composition of kernel launches for each entry point.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "dwf_common.h"
+
+namespace dwf {
+
+static thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    if (std::getenv("DWF_LOG")) std::fprintf(stderr, "[dwf] error %d: %s\n", code, msg.c_str());
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(DWF_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int batch_plan(const dwf_ctx *ctxs, int nlat, const int *nrhs, int prec, int dagger, dwf_batch *out);
+int batch_capture(dwf_batch p, void *const *outs, const void *const *ins, int out_parity, hipStream_t st);
+int batch_launch(dwf_batch p, hipStream_t st);
+int batch_free(dwf_batch p);
+
+static bool valid_prec(int p) { return p >= DWF_F64 && p <= DWF_BF16; }
+
+#define CHECK(cond, msg)                                  \
+    do {                                                  \
+        if (!(cond)) return ::dwf::fail(DWF_EINVAL, msg); \
+    } while (0)
+
+#define CHECK_CTX(ctx) CHECK((ctx) != nullptr, "null context")
+#define CHECK_GAUGE(ctx)                                                                        \
+    do {                                                                                        \
+        if (!(ctx)->gauge_set) return ::dwf::fail(DWF_EUNSUP, "gauge field not set (dwf_set_gauge)"); \
+    } while (0)
+
+// Tuned launch shapes survive contexts: keyed by (prec, dagger, dims, Ls).
+static std::mutex g_tune_mu;
+static std::map<std::string, DhopShape> g_tune;
+static bool g_tune_loaded = false;
+
+static std::string tune_key(const Geom &g, int prec, int dagger) {
+    std::ostringstream k;
+    k << prec << ' ' << dagger << ' ' << g.L[0] << ' ' << g.L[1] << ' ' << g.L[2] << ' ' << g.L[3] << ' ' << g.Ls;
+    return k.str();
+}
+
+static void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = std::getenv("DWF_TUNE_CACHE");
+    if (!path) return;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        int p, d, l0, l1, l2, l3, ls, spb, xcd;
+        if (is >> p >> d >> l0 >> l1 >> l2 >> l3 >> ls >> spb >> xcd) {
+            std::ostringstream k;
+            k << p << ' ' << d << ' ' << l0 << ' ' << l1 << ' ' << l2 << ' ' << l3 << ' ' << ls;
+            DhopShape s;
+            s.spb = spb;
+            s.xcd = xcd;
+            g_tune[k.str()] = s;
+        }
+    }
+}
+
+static void apply_tuned(dwf_ctx ctx) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    for (int p = 0; p < 4; ++p)
+        for (int d = 0; d < 2; ++d) {
+            auto it = g_tune.find(tune_key(ctx->g, p, d));
+            ctx->shape[p][d] = it != g_tune.end() ? it->second : default_shape(ctx->g);
+        }
+}
+
+static long cb_complex(const Geom &g) { return g.half * g.Ls * 12; }
+
+}  // namespace dwf
+
+using namespace dwf;
+
+extern "C" {
+
+const char *dwf_last_error(void) { return g_err.c_str(); }
+
+int dwf_create(const dwf_geom *geom, dwf_ctx *out) {
+    CHECK(geom != nullptr && out != nullptr, "dwf_create: null argument");
+    *out = nullptr;
+    for (int m = 0; m < 4; ++m)
+        CHECK(geom->dims[m] >= 2 && geom->dims[m] % 2 == 0, "dwf_create: every extent must be even and >= 2");
+    CHECK(geom->Ls >= 1 && geom->Ls <= kMaxLs, "dwf_create: Ls must be in [1, 64]");
+    CHECK(std::isfinite(geom->M5) && std::isfinite(geom->mf), "dwf_create: M5 and mf must be finite");
+    CHECK(std::fabs(5.0 - geom->M5) > 1e-12, "dwf_create: M5 = 5 makes M5op singular");
+    const long vol = (long)geom->dims[0] * geom->dims[1] * geom->dims[2] * geom->dims[3];
+    CHECK(vol / 2 * geom->Ls * 24 < (1L << 40), "dwf_create: lattice too large");
+    dwf_ctx c = new (std::nothrow) dwf_ctx_s();
+    if (!c) return fail(DWF_ENOMEM, "dwf_create: out of host memory");
+    for (int m = 0; m < 4; ++m) c->g.L[m] = geom->dims[m];
+    c->g.Ls = geom->Ls;
+    c->g.vol = vol;
+    c->g.half = vol / 2;
+    c->g.M5 = geom->M5;
+    c->g.mf = geom->mf;
+    c->g.antiperiodic = geom->antiperiodic_t ? 1 : 0;
+    auto cleanup = [&](int code, const char *msg) {
+        dwf_destroy(c);
+        return fail(code, msg);
+    };
+    if (hipGetDevice(&c->device) != hipSuccess) return cleanup(DWF_EHIP, "dwf_create: no HIP device");
+    if (std::getenv("DWF_TEST_FAIL_ALLOC")) return cleanup(DWF_ENOMEM, "dwf_create: allocation failure forced");
+    for (int p = 0; p < 4; ++p)
+        for (int par = 0; par < 2; ++par)
+            if (hipMalloc(&c->links[p][par], link_bytes(c->g, p)) != hipSuccess)
+                return cleanup(DWF_ENOMEM, "dwf_create: hipMalloc of link tables failed");
+    for (int k = 0; k < 2; ++k)
+        if (hipMalloc(&c->tmp[k], cb_bytes(c->g, DWF_F64)) != hipSuccess)
+            return cleanup(DWF_ENOMEM, "dwf_create: hipMalloc of temporaries failed");
+    if (hipMalloc(&c->partials, sizeof(double) * 2 * kRedBlocks) != hipSuccess ||
+        hipMalloc(&c->scal, sizeof(double) * 16) != hipSuccess)
+        return cleanup(DWF_ENOMEM, "dwf_create: hipMalloc of reduction buffers failed");
+    if (hipHostMalloc((void **)&c->host_scal, sizeof(double) * 16, hipHostMallocDefault) != hipSuccess)
+        return cleanup(DWF_ENOMEM, "dwf_create: pinned host allocation failed");
+    for (int k = 0; k < 2; ++k)
+        if (hipEventCreateWithFlags((hipEvent_t *)&c->events[k], hipEventDisableTiming) != hipSuccess)
+            return cleanup(DWF_EHIP, "dwf_create: hipEventCreate failed");
+    if (hipMemset(c->scal, 0, sizeof(double) * 16) != hipSuccess)
+        return cleanup(DWF_EHIP, "dwf_create: hipMemset failed");
+    apply_tuned(c);
+    *out = c;
+    return DWF_OK;
+}
+
+int dwf_destroy(dwf_ctx c) {
+    if (!c) return DWF_OK;
+    hipDeviceSynchronize();
+    for (auto &pp : c->links)
+        for (void *p : pp) hipFree(p);
+    for (void *p : c->tmp) hipFree(p);
+    hipFree(c->partials);
+    hipFree(c->scal);
+    if (c->host_scal) hipHostFree(c->host_scal);
+    for (void *e : c->events)
+        if (e) hipEventDestroy((hipEvent_t)e);
+    CgWork &w = c->work;
+    for (void *p : {w.x64, w.r64, w.p64, w.ap64, w.e32, w.r32, w.p32, w.ap32, w.p16, w.full_tmp}) hipFree(p);
+    delete c;
+    return DWF_OK;
+}
+
+int dwf_field_bytes(dwf_ctx ctx, int prec, int full, size_t *bytes) {
+    CHECK_CTX(ctx);
+    CHECK(valid_prec(prec), "dwf_field_bytes: bad precision");
+    CHECK(bytes != nullptr, "dwf_field_bytes: null output");
+    *bytes = cb_bytes(ctx->g, prec) * (full ? 2 : 1);
+    return DWF_OK;
+}
+
+int dwf_set_gauge(dwf_ctx ctx, const double *U, void *stream) {
+    CHECK_CTX(ctx);
+    CHECK(U != nullptr, "dwf_set_gauge: null gauge pointer");
+    hipStream_t st = (hipStream_t)stream;
+    for (int p = 0; p < 4; ++p)
+        for (int par = 0; par < 2; ++par) {
+            int rc = launch_gather_links(ctx->g, ctx->links[p][par], U, par, p, st);
+            if (rc) return rc;
+        }
+    ctx->gauge_set = true;
+    return DWF_OK;
+}
+
+int dwf_pack(dwf_ctx ctx, void *internal, const double *canonical, int parity, int prec, void *stream) {
+    CHECK_CTX(ctx);
+    CHECK(internal && canonical, "dwf_pack: null pointer");
+    CHECK(parity >= 0 && parity <= 2, "dwf_pack: parity must be 0, 1 or 2 (full)");
+    CHECK(valid_prec(prec), "dwf_pack: bad precision");
+    return launch_pack(ctx->g, internal, canonical, parity, prec, (hipStream_t)stream);
+}
+
+int dwf_unpack(dwf_ctx ctx, double *canonical, const void *internal, int parity, int prec, void *stream) {
+    CHECK_CTX(ctx);
+    CHECK(internal && canonical, "dwf_unpack: null pointer");
+    CHECK(parity >= 0 && parity <= 2, "dwf_unpack: parity must be 0, 1 or 2 (full)");
+    CHECK(valid_prec(prec), "dwf_unpack: bad precision");
+    return launch_unpack(ctx->g, canonical, internal, parity, prec, (hipStream_t)stream);
+}
+
+int dwf_convert(dwf_ctx ctx, void *out, int out_prec, const void *in, int in_prec, int full, void *stream) {
+    CHECK_CTX(ctx);
+    CHECK(out && in, "dwf_convert: null pointer");
+    CHECK(valid_prec(out_prec) && valid_prec(in_prec), "dwf_convert: bad precision");
+    CHECK(out != in || out_prec == in_prec, "dwf_convert: in-place conversion between precisions");
+    return launch_convert(ctx->g, out, out_prec, in, in_prec, full ? 2 : 1, (hipStream_t)stream);
+}
+
+int dwf_dhop(dwf_ctx ctx, void *out, const void *in, int out_parity, int dagger, int prec, void *stream) {
+    CHECK_CTX(ctx);
+    CHECK_GAUGE(ctx);
+    CHECK(out && in, "dwf_dhop: null pointer");
+    CHECK(out != in, "dwf_dhop: in and out must not alias");
+    CHECK(out_parity == 0 || out_parity == 1, "dwf_dhop: out_parity must be 0 or 1");
+    CHECK(dagger == 0 || dagger == 1, "dwf_dhop: dagger must be 0 or 1");
+    CHECK(valid_prec(prec), "dwf_dhop: bad precision");
+    DhopCall c{in, out, nullptr, out_parity, dagger, EPI_SCALE, 1.0, 0.0, prec, prec};
+    return launch_dhop(ctx, c, ctx->shape[prec][dagger], (hipStream_t)stream);
+}
+
+int dwf_m5(dwf_ctx ctx, void *out, const void *in, int dagger, int inverse, int full, int prec, void *stream) {
+    CHECK_CTX(ctx);
+    CHECK(out && in, "dwf_m5: null pointer");
+    CHECK((dagger == 0 || dagger == 1) && (inverse == 0 || inverse == 1), "dwf_m5: dagger/inverse must be 0 or 1");
+    CHECK(valid_prec(prec), "dwf_m5: bad precision");
+    return launch_m5(ctx->g, out, in, dagger, inverse, ctx->g.half * (full ? 2 : 1), prec, (hipStream_t)stream);
+}
+
+int dwf_mpc(dwf_ctx ctx, void *out, const void *in, int dagger, int prec, void *stream) {
+    CHECK_CTX(ctx);
+    CHECK_GAUGE(ctx);
+    CHECK(out && in && out != in, "dwf_mpc: null or aliased pointer");
+    CHECK(dagger == 0 || dagger == 1, "dwf_mpc: dagger must be 0 or 1");
+    CHECK(valid_prec(prec), "dwf_mpc: bad precision");
+    return op_mpc(ctx, out, in, dagger, prec, (hipStream_t)stream);
+}
+
+int dwf_mdagm(dwf_ctx ctx, void *out, const void *in, int prec, void *stream) {
+    CHECK_CTX(ctx);
+    CHECK_GAUGE(ctx);
+    CHECK(out && in && out != in, "dwf_mdagm: null or aliased pointer");
+    CHECK(valid_prec(prec), "dwf_mdagm: bad precision");
+    return op_mdagm(ctx, out, in, prec, ctx->tmp[1], (hipStream_t)stream);
+}
+
+int dwf_dw(dwf_ctx ctx, void *out, const void *in, int dagger, int prec, void *stream) {
+    CHECK_CTX(ctx);
+    CHECK_GAUGE(ctx);
+    CHECK(out && in && out != in, "dwf_dw: null or aliased pointer");
+    CHECK(dagger == 0 || dagger == 1, "dwf_dw: dagger must be 0 or 1");
+    CHECK(valid_prec(prec), "dwf_dw: bad precision");
+    const size_t cb = cb_bytes(ctx->g, prec);
+    const char *i = (const char *)in;
+    char *o = (char *)out;
+    hipStream_t st = (hipStream_t)stream;
+    // out_p = M5op in_p - 1/2 D_h^{p<-1-p} in_{1-p}
+    for (int p = 0; p < 2; ++p) {
+        DhopCall c{i + (1 - p) * cb, o + p * cb, i + p * cb, p, dagger, EPI_M5, -0.5, 0.0, prec, prec};
+        int rc = launch_dhop(ctx, c, ctx->shape[prec][dagger], st);
+        if (rc) return rc;
+    }
+    return DWF_OK;
+}
+
+int dwf_norm2(dwf_ctx ctx, double *result, const void *x, int full, int prec, void *stream) {
+    CHECK_CTX(ctx);
+    CHECK(result && x, "dwf_norm2: null pointer");
+    CHECK(valid_prec(prec), "dwf_norm2: bad precision");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = launch_reduce(ctx->partials, ctx->scal + 8, x, nullptr, cb_complex(ctx->g) * (full ? 2 : 1), prec, 0, st);
+    if (rc) return rc;
+    DWF_HIP(hipMemcpyAsync(ctx->host_scal, ctx->scal + 8, sizeof(double), hipMemcpyDeviceToHost, st));
+    DWF_HIP(hipStreamSynchronize(st));
+    *result = ctx->host_scal[0];
+    return DWF_OK;
+}
+
+int dwf_cdot(dwf_ctx ctx, double *result, const void *x, const void *y, int full, int prec, void *stream) {
+    CHECK_CTX(ctx);
+    CHECK(result && x && y, "dwf_cdot: null pointer");
+    CHECK(valid_prec(prec), "dwf_cdot: bad precision");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = launch_reduce(ctx->partials, ctx->scal + 8, x, y, cb_complex(ctx->g) * (full ? 2 : 1), prec, 1, st);
+    if (rc) return rc;
+    DWF_HIP(hipMemcpyAsync(ctx->host_scal, ctx->scal + 8, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    DWF_HIP(hipStreamSynchronize(st));
+    result[0] = ctx->host_scal[0];
+    result[1] = ctx->host_scal[1];
+    return DWF_OK;
+}
+
+int dwf_axpy(dwf_ctx ctx, void *y, double a_re, double a_im, const void *x, int full, int prec, void *stream) {
+    CHECK_CTX(ctx);
+    CHECK(y && x, "dwf_axpy: null pointer");
+    CHECK(valid_prec(prec), "dwf_axpy: bad precision");
+    return launch_axpy(y, a_re, a_im, x, cb_complex(ctx->g) * (full ? 2 : 1), prec, (hipStream_t)stream);
+}
+
+int dwf_cg_set_inner(dwf_ctx ctx, double inner_tol, int inner_maxit) {
+    CHECK_CTX(ctx);
+    ctx->inner_tol = inner_tol > 0 ? inner_tol : 0.0;
+    ctx->inner_maxit = inner_maxit > 0 ? inner_maxit : 0;
+    return DWF_OK;
+}
+
+int dwf_cg(dwf_ctx ctx, void *x, const void *b, double tol, int maxit, int mode, dwf_cg_stats *stats, void *stream) {
+    CHECK_CTX(ctx);
+    CHECK_GAUGE(ctx);
+    CHECK(x && b && x != b, "dwf_cg: null or aliased pointer");
+    CHECK(tol > 0 && std::isfinite(tol), "dwf_cg: tol must be positive");
+    CHECK(maxit >= 1, "dwf_cg: maxit must be >= 1");
+    CHECK(mode >= 0 && mode <= 3, "dwf_cg: mode must be 0..3");
+    return cg_solve(ctx, x, b, tol, maxit, mode, stats, (hipStream_t)stream);
+}
+
+int dwf_solve(dwf_ctx ctx, void *x, const void *b, int dagger, double tol, int maxit, int mode, dwf_cg_stats *stats,
+              void *stream) {
+    CHECK_CTX(ctx);
+    CHECK_GAUGE(ctx);
+    CHECK(x && b && x != b, "dwf_solve: null or aliased pointer");
+    CHECK(dagger == 0 || dagger == 1, "dwf_solve: dagger must be 0 or 1");
+    CHECK(tol > 0 && std::isfinite(tol), "dwf_solve: tol must be positive");
+    CHECK(maxit >= 1, "dwf_solve: maxit must be >= 1");
+    CHECK(mode >= 0 && mode <= 3, "dwf_solve: mode must be 0..3");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t cb = cb_bytes(ctx->g, DWF_F64);
+    int rc;
+    const char *be = (const char *)b, *bo = be + cb;
+    char *xe = (char *)x, *xo = xe + cb;
+    // 1. t = M5op^-1 b_e  (into x_e, overwritten at the end)
+    if ((rc = launch_m5(ctx->g, xe, be, dagger, 1, ctx->g.half, DWF_F64, st))) return rc;
+    // 2. bh = b_o + 1/2 D^{o<-e} t   (into x_o)
+    DhopCall c1{xe, xo, bo, 1, dagger, EPI_AXPY, 0.5, 1.0, DWF_F64, DWF_F64};
+    if ((rc = launch_dhop(ctx, c1, ctx->shape[DWF_F64][dagger], st))) return rc;
+    dwf_cg_stats s{0, 0, 0.0, 0.0};
+    if (!dagger) {
+        // 3. rhs = M_pc^dag bh (into x_e slot), x_o = CG solution from zero
+        if ((rc = op_mpc(ctx, xe, xo, 1, DWF_F64, st))) return rc;
+        DWF_HIP(hipMemsetAsync(xo, 0, cb, st));
+        rc = cg_solve(ctx, xo, xe, tol, maxit, mode, &s, st);
+        if (rc && rc != DWF_ENOCONV) return rc;
+    } else {
+        // 3'. y = (M_pc^dag M_pc)^-1 bh (into x_e slot), x_o = M_pc y
+        DWF_HIP(hipMemsetAsync(xe, 0, cb, st));
+        rc = cg_solve(ctx, xe, xo, tol, maxit, mode, &s, st);
+        if (rc && rc != DWF_ENOCONV) return rc;
+        int rc2 = op_mpc(ctx, xo, xe, 0, DWF_F64, st);
+        if (rc2) return rc2;
+    }
+    // 4. x_e = M5op^-1 (b_e + 1/2 D^{e<-o} x_o)
+    DhopCall c2{xo, xe, be, 0, dagger, EPI_M5INV, 0.5, 1.0, DWF_F64, DWF_F64};
+    int rc3 = launch_dhop(ctx, c2, ctx->shape[DWF_F64][dagger], st);
+    if (rc3) return rc3;
+    DWF_HIP(hipStreamSynchronize(st));
+    if (stats) *stats = s;
+    return rc;
+}
+
+int dwf_force(dwf_ctx ctx, double *F, const void *X, const void *Y, int kind, double scale, void *stream) {
+    CHECK_CTX(ctx);
+    CHECK(F && X && Y, "dwf_force: null pointer");
+    CHECK(kind == 0 || kind == 1, "dwf_force: kind must be 0 or 1");
+    if (kind == 1) CHECK_GAUGE(ctx);
+    return launch_force(ctx, F, X, Y, kind, scale, (hipStream_t)stream);
+}
+
+int dwf_batch_plan(const dwf_ctx *ctxs, int nlat, const int *nrhs, int prec, int dagger, dwf_batch *plan) {
+    CHECK(ctxs && nrhs && plan, "dwf_batch_plan: null pointer");
+    CHECK(nlat >= 1 && nlat <= 16, "dwf_batch_plan: nlat must be in [1, 16]");
+    CHECK(valid_prec(prec), "dwf_batch_plan: bad precision");
+    CHECK(dagger == 0 || dagger == 1, "dwf_batch_plan: dagger must be 0 or 1");
+    for (int l = 0; l < nlat; ++l) {
+        CHECK(ctxs[l] != nullptr && nrhs[l] >= 1, "dwf_batch_plan: null context or nrhs < 1");
+        CHECK_GAUGE(ctxs[l]);
+    }
+    return batch_plan(ctxs, nlat, nrhs, prec, dagger, plan);
+}
+
+int dwf_batch_capture(dwf_batch plan, void *const *outs, const void *const *ins, int out_parity, void *stream) {
+    CHECK(plan && outs && ins, "dwf_batch_capture: null pointer");
+    CHECK(out_parity == 0 || out_parity == 1, "dwf_batch_capture: out_parity must be 0 or 1");
+    return batch_capture(plan, outs, ins, out_parity, (hipStream_t)stream);
+}
+
+int dwf_batch_launch(dwf_batch plan, void *stream) {
+    CHECK(plan, "dwf_batch_launch: null plan");
+    return batch_launch(plan, (hipStream_t)stream);
+}
+
+int dwf_batch_free(dwf_batch plan) {
+    if (!plan) return DWF_OK;
+    return batch_free(plan);
+}
+
+int dwf_tune(dwf_ctx ctx, int prec, int dagger, double *best_us, void *stream) {
+    CHECK_CTX(ctx);
+    CHECK_GAUGE(ctx);
+    CHECK(valid_prec(prec) && (dagger == 0 || dagger == 1), "dwf_tune: bad precision or dagger");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t cb = cb_bytes(ctx->g, prec);
+    void *in = nullptr, *out = nullptr;
+    if (hipMalloc(&in, cb) != hipSuccess || hipMalloc(&out, cb) != hipSuccess) {
+        hipFree(in);
+        return fail(DWF_ENOMEM, "dwf_tune: scratch allocation failed");
+    }
+    DWF_HIP(hipMemsetAsync(in, 0, cb, st));
+    std::vector<DhopShape> cand;
+    for (int threads : {64, 128, 192, 256, 320, 384, 512, 768, 1024}) {
+        if (threads % ctx->g.Ls) continue;
+        for (int xcd : {0, 1}) {
+            DhopShape s;
+            s.spb = threads / ctx->g.Ls;
+            s.xcd = xcd;
+            cand.push_back(s);
+        }
+    }
+    if (cand.empty()) {
+        DhopShape s = default_shape(ctx->g);
+        cand.push_back(s);
+    }
+    hipEvent_t e0, e1;
+    DWF_HIP(hipEventCreate(&e0));
+    DWF_HIP(hipEventCreate(&e1));
+    double best = 1e30;
+    DhopShape best_s = cand[0];
+    const int reps = 10;
+    for (const DhopShape &s : cand) {
+        DhopCall c{in, out, nullptr, 1, dagger, EPI_SCALE, 1.0, 0.0, prec, prec};
+        int rc = launch_dhop(ctx, c, s, st);  // warm-up
+        if (rc) continue;
+        DWF_HIP(hipEventRecord(e0, st));
+        for (int r = 0; r < reps; ++r) {
+            c.out_parity = r & 1;
+            launch_dhop(ctx, c, s, st);
+        }
+        DWF_HIP(hipEventRecord(e1, st));
+        DWF_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        DWF_HIP(hipEventElapsedTime(&ms, e0, e1));
+        const double us = 1000.0 * ms / reps;
+        if (us < best) {
+            best = us;
+            best_s = s;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(in);
+    hipFree(out);
+    ctx->shape[prec][dagger] = best_s;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        g_tune[tune_key(ctx->g, prec, dagger)] = best_s;
+        if (const char *path = std::getenv("DWF_TUNE_CACHE")) {
+            std::ofstream f(path, std::ios::trunc);
+            for (auto &kv : g_tune) f << kv.first << ' ' << kv.second.spb << ' ' << kv.second.xcd << '\n';
+        }
+    }
+    if (best_us) *best_us = best;
+    return DWF_OK;
+}
+
+}  // extern "C"

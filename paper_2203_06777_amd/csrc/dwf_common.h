@@ -1,0 +1,154 @@
+// Internal declarations shared by the HIP translation units of libdwf.so.
+//
+// Internal field layout ("Ls-innermost"): a checkerboard field of precision P
+// stores, for checkerboard row c, component group g and fifth coordinate s, one
+// 16-byte vector of G(P) complex numbers:
+//
+//     offset16(c, g, s) = (c * NG + g) * Ls + s,      NG = 12 / G
+//
+// with complex component k = g*G + j = spin*3 + colour.  G = 1 (FP64), 2 (FP32),
+// 4 (FP16/BF16), so every load and store is a 16-byte vector, and the Ls lanes
+// that share a 4D site read Ls consecutive vectors: one wave reads whole
+// contiguous 16*Ls-byte segments, and the site's links are fetched once and
+// broadcast to all its s lanes.  A full field is the even checkerboard followed
+// by the odd one.
+//
+// Gathered links: for output parity p and row c, 8 colour matrices
+// [c][dir][3][3] (complex, storage precision): dir = mu (0..3) holds
+// eta_mu(x) U_mu(x), dir = 4 + mu holds (eta_mu(x-mu) U_mu(x-mu))^dag, so the
+// hopping kernel multiplies every direction by a plain matrix.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/dwf.h"
+
+namespace dwf {
+
+constexpr int kMaxLs = 64;
+
+// --------------------------------------------------------------------------
+// Precision traits
+// --------------------------------------------------------------------------
+template <int P> struct PT;
+template <> struct PT<DWF_F64> { using A = double; static constexpr int G = 1; static constexpr int RB = 8; };
+template <> struct PT<DWF_F32> { using A = float;  static constexpr int G = 2; static constexpr int RB = 4; };
+template <> struct PT<DWF_F16> { using A = float;  static constexpr int G = 4; static constexpr int RB = 2; };
+template <> struct PT<DWF_BF16> { using A = float; static constexpr int G = 4; static constexpr int RB = 2; };
+
+inline int real_bytes(int prec) { return prec == DWF_F64 ? 8 : prec == DWF_F32 ? 4 : 2; }
+
+struct Geom {
+    int L[4];
+    int Ls;
+    long vol;   // 4D volume
+    long half;  // vol / 2
+    double M5, mf;
+    int antiperiodic;
+};
+
+// Bytes of one internal checkerboard field.
+inline size_t cb_bytes(const Geom &g, int prec) { return (size_t)g.half * g.Ls * 24 * real_bytes(prec); }
+inline size_t link_bytes(const Geom &g, int prec) { return (size_t)g.half * 8 * 18 * real_bytes(prec); }
+
+// Launch shape of the hopping kernel.
+struct DhopShape {
+    int spb = 0;        // 4D sites per workgroup (workgroup = spb * Ls lanes)
+    int xcd = 1;        // XCD-aware block remap on/off
+};
+
+// Epilogue modes of the hopping kernel (out is at the output parity):
+enum Epi {
+    EPI_SCALE = 0,  // out = alpha * D psi
+    EPI_AXPY = 1,   // out = beta * z + alpha * D psi
+    EPI_M5 = 2,     // out = M5op(z) + alpha * D psi   (M5op^dag when dagger)
+    EPI_M5INV = 3,  // out = M5op^-1 (beta * z + alpha * D psi)   (M5op^-dag when dagger; z optional)
+};
+
+struct DhopCall {
+    const void *in;
+    void *out;
+    const void *z;  // field at the output parity for the epilogues (may be null for EPI_M5INV)
+    int out_parity;
+    int dagger;
+    int epi;
+    double alpha, beta;
+    int prec_in, prec_out;  // links use prec_in
+};
+
+// Solver workspace (allocated on first solve).
+struct CgWork {
+    size_t bytes = 0;
+    void *x64 = nullptr, *r64 = nullptr, *p64 = nullptr, *ap64 = nullptr;
+    void *e32 = nullptr, *r32 = nullptr, *p32 = nullptr, *ap32 = nullptr, *p16 = nullptr;
+    void *full_tmp = nullptr;  // one full FP64 field for dwf_solve
+};
+
+}  // namespace dwf
+
+struct dwf_ctx_s {
+    dwf::Geom g;
+    int device = 0;
+    void *links[4][2] = {};  // [prec][output parity]
+    bool gauge_set = false;
+    void *tmp[2] = {};       // FP64-sized checkerboard temporaries for M_pc
+    double *partials = nullptr;  // reduction partials (2 * kRedBlocks doubles)
+    double *scal = nullptr;      // device scalars of the solvers
+    double *host_scal = nullptr; // pinned host mirror (16 doubles)
+    void *events[2] = {};        // hipEvent_t pair for the solver's lagged stop check
+    dwf::DhopShape shape[4][2];  // tuned launch shape per (prec, dagger)
+    double inner_tol = 0.0;
+    int inner_maxit = 0;
+    dwf::CgWork work;
+};
+
+namespace dwf {
+
+constexpr int kRedBlocks = 1024;  // fixed reduction grid: results do not depend on timing
+constexpr int kRedThreads = 256;
+
+// Error reporting (thread-local message).
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+#define DWF_HIP(call)                                            \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) return ::dwf::hip_fail(e_, #call); \
+    } while (0)
+
+// Layout kernels (layout.hip).
+int launch_pack(const Geom &g, void *internal, const double *canonical, int parity, int prec, hipStream_t st);
+int launch_unpack(const Geom &g, double *canonical, const void *internal, int parity, int prec, hipStream_t st);
+int launch_gather_links(const Geom &g, void *links, const double *U, int out_parity, int prec, hipStream_t st);
+int launch_convert(const Geom &g, void *out, int out_prec, const void *in, int in_prec, long ncb, hipStream_t st);
+
+// Hopping kernel with epilogues (dhop.hip).
+int launch_dhop(dwf_ctx ctx, const DhopCall &c, const DhopShape &shape, hipStream_t st);
+DhopShape default_shape(const Geom &g);
+// M5op family on ncb checkerboard fields (m5.hip).
+int launch_m5(const Geom &g, void *out, const void *in, int dagger, int inverse, long nsites, int prec,
+              hipStream_t st);
+void m5inv_coefficients(const Geom &g, double *coef);
+
+// BLAS-1 and reductions (blas.hip). n = number of complex elements.
+int launch_reduce(double *partials, double *dst, const void *x, const void *y, long n, int prec, int dot,
+                  hipStream_t st);
+int launch_axpy(void *y, double ar, double ai, const void *x, long n, int prec, hipStream_t st);
+
+// Operators composed from kernels (ops.hip).
+int op_mpc(dwf_ctx ctx, void *out, const void *in, int dagger, int prec, hipStream_t st);
+int op_mdagm(dwf_ctx ctx, void *out, const void *in, int prec, void *tmp_o, hipStream_t st);
+int op_mdagm_mixed(dwf_ctx ctx, void *out, int prec_out, const void *in, int prec, hipStream_t st);
+
+// Solvers (solver.hip).
+int cg_solve(dwf_ctx ctx, void *x, const void *b, double tol, int maxit, int mode, dwf_cg_stats *stats,
+             hipStream_t st);
+
+// Force (force.hip).
+int launch_force(dwf_ctx ctx, double *F, const void *X, const void *Y, int kind, double scale, hipStream_t st);
+
+}  // namespace dwf

@@ -1,0 +1,104 @@
+// Fifth-dimension (Shamir) term on its own: M5op, M5op^dag, M5op^-1, M5op^-dag.
+//
+// One lane per (4D site, s); the Ls lanes of a site exchange their spinors
+// through LDS, so the kernel reads and writes each field once and in == out
+// is allowed.  M5op couples s to s +- 1 (P_- to s+1, P_+ to s-1, with -mf on
+// the wraps); its inverse is, per chirality, the geometric series of the
+// twisted shift K (K^Ls = -mf):  (d - K)^-1 = sum_n d^-(n+1) K^n / (1 + mf d^-Ls).
+#include "dwf_device.h"
+
+namespace dwf {
+
+struct M5Args {
+    const u32x4 *in;
+    u32x4 *out;
+    long nsites;
+    int Ls, spb, dagger, inverse;
+    double d5, mf;
+    double coef[kMaxLs];
+};
+
+template <int P>
+__global__ void __launch_bounds__(1024) k_m5(const M5Args a) {
+    using A = typename PT<P>::A;
+    extern __shared__ unsigned char smem[];
+    A *lds = reinterpret_cast<A *>(smem);
+    const int Ls = a.Ls;
+    const int j = threadIdx.x / Ls;
+    const int s = threadIdx.x - j * Ls;
+    const long c = (long)blockIdx.x * a.spb + j;
+    const bool active = c < a.nsites;
+    A v[24];
+    if (active) load_spinor<P>(a.in, c, Ls, s, v);
+    else
+#pragma unroll
+        for (int k = 0; k < 24; ++k) v[k] = 0;
+    A *mine = lds + (j * Ls + s) * 25;
+#pragma unroll
+    for (int k = 0; k < 24; ++k) mine[k] = v[k];
+    __syncthreads();
+    if (!active) return;
+    const A *site = lds + j * Ls * 25;
+    const A mf = (A)a.mf;
+    A o[24];
+    if (!a.inverse) {
+        const int su = s + 1 < Ls ? s + 1 : 0, sd = s >= 1 ? s - 1 : Ls - 1;
+        const A fu = s + 1 < Ls ? (A)1 : -mf, fd = s >= 1 ? (A)1 : -mf;
+        const A *zu = site + su * 25, *zd = site + sd * 25;
+        const A d5 = (A)a.d5;
+        // upper spins: P_+ takes s-1 (adjoint: s+1); lower spins: P_- takes s+1 (adjoint: s-1)
+#pragma unroll
+        for (int k = 0; k < 12; ++k) o[k] = d5 * v[k] - (a.dagger ? fu * zu[k] : fd * zd[k]);
+#pragma unroll
+        for (int k = 12; k < 24; ++k) o[k] = d5 * v[k] - (a.dagger ? fd * zd[k] : fu * zu[k]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) o[k] = 0;
+        for (int n = 0; n < Ls; ++n) {
+            const A cf = (A)a.coef[n];
+            int sp = s + n;
+            const A fp = sp < Ls ? cf : -mf * cf;
+            sp = sp < Ls ? sp : sp - Ls;
+            int sm = s - n;
+            const A fm = sm >= 0 ? cf : -mf * cf;
+            sm = sm >= 0 ? sm : sm + Ls;
+            const A *vu = site + (a.dagger ? sp : sm) * 25;
+            const A *vl = site + (a.dagger ? sm : sp) * 25;
+            const A fu = a.dagger ? fp : fm, fl = a.dagger ? fm : fp;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) o[k] += fu * vu[k];
+#pragma unroll
+            for (int k = 12; k < 24; ++k) o[k] += fl * vl[k];
+        }
+    }
+    store_spinor<P>(a.out, c, Ls, s, o);
+}
+
+int launch_m5(const Geom &g, void *out, const void *in, int dagger, int inverse, long nsites, int prec,
+              hipStream_t st) {
+    M5Args a;
+    a.in = (const u32x4 *)in;
+    a.out = (u32x4 *)out;
+    a.nsites = nsites;
+    a.Ls = g.Ls;
+    a.spb = default_shape(g).spb;
+    a.dagger = dagger;
+    a.inverse = inverse;
+    a.d5 = 5.0 - g.M5;
+    a.mf = g.mf;
+    m5inv_coefficients(g, a.coef);
+    const int threads = a.spb * g.Ls;
+    const unsigned nb = (unsigned)((nsites + a.spb - 1) / a.spb);
+    const size_t areal = prec == DWF_F64 ? 8 : 4;
+    const size_t shm = (size_t)threads * 25 * areal;
+    switch (prec) {
+        case DWF_F64: hipLaunchKernelGGL(k_m5<DWF_F64>, nb, threads, shm, st, a); break;
+        case DWF_F32: hipLaunchKernelGGL(k_m5<DWF_F32>, nb, threads, shm, st, a); break;
+        case DWF_F16: hipLaunchKernelGGL(k_m5<DWF_F16>, nb, threads, shm, st, a); break;
+        default: hipLaunchKernelGGL(k_m5<DWF_BF16>, nb, threads, shm, st, a); break;
+    }
+    DWF_HIP(hipGetLastError());
+    return DWF_OK;
+}
+
+}  // namespace dwf

@@ -1,0 +1,329 @@
+// Conjugate gradient on the Schur normal operator M_pc^dag M_pc, in FP64 and
+// as FP64 defect correction around a low-precision inner CG.
+//
+// The CG scalars (alpha, beta, |r|^2, the stop flag) live in device memory and
+// are produced by single-block kernels from the FP64 block partials, so an
+// iteration is a fixed sequence of launches with no host round trip.  The host
+// reads the stop flag one iteration behind (an async copy into pinned memory
+// and an event), so the GPU queue never drains; once the flag is set, the
+// update kernels of any iteration already queued leave x, r and p untouched.
+#include <chrono>
+#include <cmath>
+
+#include "dwf_device.h"
+
+namespace dwf {
+
+enum { S_RR = 0, S_PAP = 1, S_ALPHA = 2, S_BETA = 3, S_STOP = 4, S_DONE = 5, S_ITERS = 6, S_RED = 8 };
+constexpr int kScal = 16;
+
+__device__ inline void block_sum1(double &a) {
+    __shared__ double sa[kRedThreads / 64];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) a += __shfl_xor(a, off, 64);
+    if (threadIdx.x % 64 == 0) sa[threadIdx.x / 64] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = 0;
+        for (int k = 0; k < kRedThreads / 64; ++k) a += sa[k];
+    }
+}
+
+__device__ inline double sum_partials(const double *partials) {
+    double v = 0;
+    for (int k = threadIdx.x; k < kRedBlocks; k += kRedThreads) v += partials[2 * k];
+    block_sum1(v);
+    return v;
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_cg_alpha(double *scal, const double *partials) {
+    const double pap = sum_partials(partials);
+    if (threadIdx.x != 0 || scal[S_DONE] != 0) return;
+    scal[S_PAP] = pap;
+    if (!isfinite(pap) || pap <= 0.0) {
+        scal[S_DONE] = 2;
+        return;
+    }
+    scal[S_ALPHA] = scal[S_RR] / pap;
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_cg_beta(double *scal, const double *partials) {
+    const double rr = sum_partials(partials);
+    if (threadIdx.x != 0 || scal[S_DONE] != 0) return;
+    scal[S_ITERS] += 1;
+    if (!isfinite(rr)) {
+        scal[S_DONE] = 2;
+        return;
+    }
+    scal[S_BETA] = rr / scal[S_RR];
+    scal[S_RR] = rr;
+    if (rr <= scal[S_STOP]) scal[S_DONE] = 1;
+}
+
+// x += alpha p ; r -= alpha Ap ; partial |r|^2.
+template <int P>
+__global__ void __launch_bounds__(kRedThreads) k_cg_xr(u32x4 *x, u32x4 *r, const u32x4 *p, const u32x4 *ap,
+                                                       const double *scal, double *partials, long nv) {
+    if (scal[S_DONE] != 0) return;
+    constexpr int R = 2 * PT<P>::G;
+    using A = typename PT<P>::A;
+    const A alpha = (A)scal[S_ALPHA];
+    double acc = 0;
+    for (long v = (long)blockIdx.x * kRedThreads + threadIdx.x; v < nv; v += (long)gridDim.x * kRedThreads) {
+        A xv[R], rv[R], pv[R], av[R];
+        unpack16<P>(x[v], xv);
+        unpack16<P>(r[v], rv);
+        unpack16<P>(p[v], pv);
+        unpack16<P>(ap[v], av);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            xv[k] += alpha * pv[k];
+            rv[k] -= alpha * av[k];
+            acc += (double)rv[k] * rv[k];
+        }
+        x[v] = pack16<P>(xv);
+        r[v] = pack16<P>(rv);
+    }
+    block_sum1(acc);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = acc;
+        partials[2 * blockIdx.x + 1] = 0;
+    }
+}
+
+// p = r + beta p, optionally also storing p in the 16-bit operator precision.
+template <int P, int P16>
+__global__ void __launch_bounds__(256) k_cg_p(u32x4 *p, const u32x4 *r, u32x4 *p16, const double *scal, long nrows,
+                                              int Ls) {
+    if (scal[S_DONE] != 0) return;
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= nrows * Ls) return;
+    const long c = t / Ls;
+    const int s = (int)(t - c * Ls);
+    using A = typename PT<P>::A;
+    const A beta = (A)scal[S_BETA];
+    A pv[24], rv[24];
+    load_spinor<P>(p, c, Ls, s, pv);
+    load_spinor<P>(r, c, Ls, s, rv);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) pv[k] = rv[k] + beta * pv[k];
+    store_spinor<P>(p, c, Ls, s, pv);
+    if (P16 >= 0) store_spinor<(P16 < 0 ? P : P16)>(p16, c, Ls, s, pv);
+}
+
+// out = factor * in with a precision change.
+template <int PI, int PO>
+__global__ void __launch_bounds__(256) k_convert_scale(u32x4 *out, const u32x4 *in, double factor, long nrows,
+                                                       int Ls) {
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= nrows * Ls) return;
+    const long c = t / Ls;
+    const int s = (int)(t - c * Ls);
+    double v[24];
+    load_spinor<PI>(in, c, Ls, s, v);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) v[k] *= factor;
+    store_spinor<PO>(out, c, Ls, s, v);
+}
+
+// y (FP64) += a * x (FP32).
+__global__ void __launch_bounds__(256) k_axpy_f32_to_f64(u32x4 *y, const u32x4 *x, double a, long nrows, int Ls) {
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= nrows * Ls) return;
+    const long c = t / Ls;
+    const int s = (int)(t - c * Ls);
+    double yv[24], xv[24];
+    load_spinor<DWF_F64>(y, c, Ls, s, yv);
+    load_spinor<DWF_F32>(x, c, Ls, s, xv);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) yv[k] += a * xv[k];
+    store_spinor<DWF_F64>(y, c, Ls, s, yv);
+}
+
+__global__ void k_set_scalars(double *scal, double stop) {
+    if (threadIdx.x != 0) return;
+    scal[S_RR] = scal[S_RED];
+    scal[S_STOP] = stop;
+    scal[S_DONE] = 0;
+    scal[S_ITERS] = 0;
+}
+
+static inline unsigned nb256(long n) { return (unsigned)((n + 255) / 256); }
+
+static int ensure_work(dwf_ctx ctx) {
+    CgWork &w = ctx->work;
+    if (w.x64) return DWF_OK;
+    const Geom &g = ctx->g;
+    const size_t b64 = cb_bytes(g, DWF_F64), b32 = cb_bytes(g, DWF_F32), b16 = cb_bytes(g, DWF_F16);
+    void **f64[] = {&w.x64, &w.r64, &w.p64, &w.ap64};
+    void **f32[] = {&w.e32, &w.r32, &w.p32, &w.ap32};
+    for (void **p : f64)
+        if (hipMalloc(p, b64) != hipSuccess) return fail(DWF_ENOMEM, "solver workspace: hipMalloc failed");
+    for (void **p : f32)
+        if (hipMalloc(p, b32) != hipSuccess) return fail(DWF_ENOMEM, "solver workspace: hipMalloc failed");
+    if (hipMalloc(&w.p16, b16) != hipSuccess) return fail(DWF_ENOMEM, "solver workspace: hipMalloc failed");
+    if (hipMalloc(&w.full_tmp, 2 * b64) != hipSuccess) return fail(DWF_ENOMEM, "solver workspace: hipMalloc failed");
+    w.bytes = 4 * b64 + 4 * b32 + b16 + 2 * b64;
+    return DWF_OK;
+}
+
+// Synchronous FP64 norm of an internal field.
+static int norm2_sync(dwf_ctx ctx, const void *x, int prec, double *out, hipStream_t st) {
+    const long n = ctx->g.half * ctx->g.Ls * 12;
+    int rc = launch_reduce(ctx->partials, ctx->scal + S_RED, x, nullptr, n, prec, 0, st);
+    if (rc) return rc;
+    DWF_HIP(hipMemcpyAsync(ctx->host_scal, ctx->scal + S_RED, sizeof(double), hipMemcpyDeviceToHost, st));
+    DWF_HIP(hipStreamSynchronize(st));
+    *out = ctx->host_scal[0];
+    return DWF_OK;
+}
+
+// Plain CG iterations on A e = r from the current (x, r): p = r, until
+// |r|^2 <= stop_rr or the iteration budget is used.  vprec is the vector
+// precision (F64 or F32); oprec the operator precision (p is additionally
+// kept in oprec when that is a 16-bit format).
+static int cg_core(dwf_ctx ctx, int vprec, int oprec, void *x, void *r, void *p, void *ap, double stop_rr,
+                   int budget, int *iters_out, int *status_out, hipStream_t st) {
+    const Geom &g = ctx->g;
+    const long n = g.half * g.Ls * 12;
+    const long nv = vprec == DWF_F64 ? n : n / 2;
+    const size_t bytes = cb_bytes(g, vprec);
+    const bool sixteen = oprec == DWF_F16 || oprec == DWF_BF16;
+    void *p16 = ctx->work.p16;
+    int rc;
+    // |r|^2 -> scal[S_RED] -> scal[S_RR]
+    if ((rc = launch_reduce(ctx->partials, ctx->scal + S_RED, r, nullptr, n, vprec, 0, st))) return rc;
+    hipLaunchKernelGGL(k_set_scalars, 1, 64, 0, st, ctx->scal, stop_rr);
+    DWF_HIP(hipMemcpyAsync(p, r, bytes, hipMemcpyDeviceToDevice, st));
+    if (sixteen) {
+        if (oprec == DWF_F16)
+            hipLaunchKernelGGL((k_convert_scale<DWF_F32, DWF_F16>), nb256(g.half * g.Ls), 256, 0, st, (u32x4 *)p16,
+                               (const u32x4 *)p, 1.0, g.half, g.Ls);
+        else
+            hipLaunchKernelGGL((k_convert_scale<DWF_F32, DWF_BF16>), nb256(g.half * g.Ls), 256, 0, st, (u32x4 *)p16,
+                               (const u32x4 *)p, 1.0, g.half, g.Ls);
+    }
+    hipEvent_t ev[2] = {(hipEvent_t)ctx->events[0], (hipEvent_t)ctx->events[1]};
+    double *hs = ctx->host_scal;
+    int it = 0, status = 0;
+    for (; it < budget; ++it) {
+        // Ap
+        if (vprec == DWF_F64) rc = op_mdagm(ctx, ap, p, DWF_F64, ctx->tmp[1], st);
+        else if (sixteen) rc = op_mdagm_mixed(ctx, ap, DWF_F32, p16, oprec, st);
+        else rc = op_mdagm(ctx, ap, p, DWF_F32, ctx->tmp[1], st);
+        if (rc) return rc;
+        // <p, Ap> -> alpha
+        if ((rc = launch_reduce(ctx->partials, nullptr, p, ap, n, vprec, 1, st))) return rc;
+        hipLaunchKernelGGL(k_cg_alpha, 1, kRedThreads, 0, st, ctx->scal, ctx->partials);
+        // x, r update and |r|^2 -> beta, stop flag
+        if (vprec == DWF_F64)
+            hipLaunchKernelGGL(k_cg_xr<DWF_F64>, kRedBlocks, kRedThreads, 0, st, (u32x4 *)x, (u32x4 *)r,
+                               (const u32x4 *)p, (const u32x4 *)ap, ctx->scal, ctx->partials, nv);
+        else
+            hipLaunchKernelGGL(k_cg_xr<DWF_F32>, kRedBlocks, kRedThreads, 0, st, (u32x4 *)x, (u32x4 *)r,
+                               (const u32x4 *)p, (const u32x4 *)ap, ctx->scal, ctx->partials, nv);
+        hipLaunchKernelGGL(k_cg_beta, 1, kRedThreads, 0, st, ctx->scal, ctx->partials);
+        // p = r + beta p
+        const unsigned nb = nb256(g.half * g.Ls);
+        if (vprec == DWF_F64)
+            hipLaunchKernelGGL((k_cg_p<DWF_F64, -1>), nb, 256, 0, st, (u32x4 *)p, (const u32x4 *)r, nullptr,
+                               ctx->scal, g.half, g.Ls);
+        else if (oprec == DWF_F16)
+            hipLaunchKernelGGL((k_cg_p<DWF_F32, DWF_F16>), nb, 256, 0, st, (u32x4 *)p, (const u32x4 *)r,
+                               (u32x4 *)p16, ctx->scal, g.half, g.Ls);
+        else if (oprec == DWF_BF16)
+            hipLaunchKernelGGL((k_cg_p<DWF_F32, DWF_BF16>), nb, 256, 0, st, (u32x4 *)p, (const u32x4 *)r,
+                               (u32x4 *)p16, ctx->scal, g.half, g.Ls);
+        else
+            hipLaunchKernelGGL((k_cg_p<DWF_F32, -1>), nb, 256, 0, st, (u32x4 *)p, (const u32x4 *)r, nullptr,
+                               ctx->scal, g.half, g.Ls);
+        DWF_HIP(hipGetLastError());
+        // stop flag, read one iteration behind
+        DWF_HIP(hipMemcpyAsync(hs + 8 * (it & 1), ctx->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+        DWF_HIP(hipEventRecord(ev[it & 1], st));
+        if (it >= 1) {
+            DWF_HIP(hipEventSynchronize(ev[(it - 1) & 1]));
+            if (hs[8 * ((it - 1) & 1) + S_DONE] != 0) {
+                ++it;
+                break;
+            }
+        }
+    }
+    DWF_HIP(hipStreamSynchronize(st));
+    DWF_HIP(hipMemcpy(hs, ctx->scal, 8 * sizeof(double), hipMemcpyDeviceToHost));
+    status = (int)hs[S_DONE];
+    *iters_out = (int)hs[S_ITERS];
+    *status_out = status;
+    (void)it;
+    return DWF_OK;
+}
+
+int cg_solve(dwf_ctx ctx, void *x, const void *b, double tol, int maxit, int mode, dwf_cg_stats *stats,
+             hipStream_t st) {
+    auto t0 = std::chrono::steady_clock::now();
+    int rc = ensure_work(ctx);
+    if (rc) return rc;
+    const Geom &g = ctx->g;
+    CgWork &w = ctx->work;
+    const long n = g.half * g.Ls * 12;
+    const size_t b64 = cb_bytes(g, DWF_F64);
+    double bb;
+    if ((rc = norm2_sync(ctx, b, DWF_F64, &bb, st))) return rc;
+    if (!std::isfinite(bb)) return fail(DWF_ENAN, "dwf_cg: right-hand side is not finite");
+    dwf_cg_stats s{0, 0, 0.0, 0.0};
+    auto finish = [&](int code) {
+        s.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (stats) *stats = s;
+        return code;
+    };
+    if (bb == 0.0) {
+        DWF_HIP(hipMemsetAsync(x, 0, b64, st));
+        DWF_HIP(hipStreamSynchronize(st));
+        return finish(DWF_OK);
+    }
+    const int oprec = mode == 1 ? DWF_F32 : mode == 2 ? DWF_F16 : DWF_BF16;
+    double inner_tol = ctx->inner_tol > 0 ? ctx->inner_tol : (mode == 1 ? 1e-5 : 1e-3);
+    int inner_maxit = ctx->inner_maxit > 0 ? ctx->inner_maxit : 2000;
+    int total = 0;
+    double rr = 0;
+    for (;;) {
+        // r = b - A x (FP64)
+        if ((rc = op_mdagm(ctx, w.ap64, x, DWF_F64, ctx->tmp[1], st))) return rc;
+        DWF_HIP(hipMemcpyAsync(w.r64, b, b64, hipMemcpyDeviceToDevice, st));
+        if ((rc = launch_axpy(w.r64, -1.0, 0.0, w.ap64, n, DWF_F64, st))) return rc;
+        if ((rc = norm2_sync(ctx, w.r64, DWF_F64, &rr, st))) return rc;
+        s.true_rel_resid = std::sqrt(rr / bb);
+        if (!std::isfinite(rr)) return finish(fail(DWF_ENAN, "dwf_cg: residual is not finite"));
+        if (s.true_rel_resid <= tol) return finish(DWF_OK);
+        if (total >= maxit) {
+            s.inner_iters = total;
+            return finish(fail(DWF_ENOCONV, "dwf_cg: iteration limit reached before tolerance"));
+        }
+        s.outer_iters += 1;
+        int it = 0, status = 0;
+        if (mode == 0) {
+            if ((rc = cg_core(ctx, DWF_F64, DWF_F64, x, w.r64, w.p64, w.ap64, tol * tol * bb, maxit - total, &it,
+                              &status, st)))
+                return rc;
+        } else {
+            // inner solve A e = r^, r^ = r * sqrt(n)/|r| in FP32 (components of order one)
+            const double scale = std::sqrt((double)n) / std::sqrt(rr);
+            hipLaunchKernelGGL((k_convert_scale<DWF_F64, DWF_F32>), nb256(g.half * g.Ls), 256, 0, st,
+                               (u32x4 *)w.r32, (const u32x4 *)w.r64, scale, g.half, g.Ls);
+            DWF_HIP(hipMemsetAsync(w.e32, 0, cb_bytes(g, DWF_F32), st));
+            const int budget = std::min(inner_maxit, maxit - total);
+            if ((rc = cg_core(ctx, DWF_F32, oprec, w.e32, w.r32, w.p32, w.ap32,
+                              inner_tol * inner_tol * (double)n, budget, &it, &status, st)))
+                return rc;
+            hipLaunchKernelGGL(k_axpy_f32_to_f64, nb256(g.half * g.Ls), 256, 0, st, (u32x4 *)x,
+                               (const u32x4 *)w.e32, 1.0 / scale, g.half, g.Ls);
+            DWF_HIP(hipGetLastError());
+        }
+        total += it;
+        s.inner_iters = total;
+        if (status == 2) return finish(fail(DWF_ENAN, "dwf_cg: non-finite value in the iteration"));
+        if (it == 0) return finish(fail(DWF_ENOCONV, "dwf_cg: no progress"));
+    }
+}
+
+}  // namespace dwf
