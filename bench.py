@@ -129,6 +129,18 @@ def main():
     parity_err = float(np.linalg.norm(got - want) / np.linalg.norm(want))
     log(f"sampled parity rel-L2 {parity_err:.2e}")
 
+    # ---------------- plain copy of known size (bandwidth and counter calibration) ----------------
+    nbytes = 1 << 30
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    copy_ms = timed(lambda: dst.copy_(src), 10, torch)
+    copy_gbs = 2 * nbytes / (copy_ms * 1e-3) / 1e9
+    log(f"copy 1 GiB -> 1 GiB: {copy_ms * 1e3:.1f} us, {copy_gbs:.0f} GB/s (read+write)")
+    del src, dst
+    torch.cuda.empty_cache()
+
     # ---------------- secondary rows ----------------
     def dhop_row(prec, rb):
         fin[prec] = (op.pack(torch.from_numpy(psi).cuda(), 0, prec), op.pack(torch.from_numpy(psi).cuda(), 1, prec))
@@ -197,6 +209,8 @@ def main():
                      "kernel": "k_dhop<F32,F32,0,EPI_SCALE>", "algorithmic_bytes_per_launch": algo_bytes,
                      "us_per_launch": round(apply_ms * 1e3, 2)},
         "parity_rel_l2_sampled": parity_err,
+        "copy_gbs": round(copy_gbs, 1),
+        "frac_of_copy": round(achieved / copy_gbs, 4),
         "cpu_baseline": cpu,
         "rows": rows,
     }

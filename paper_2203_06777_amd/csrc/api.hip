@@ -66,13 +66,14 @@ static void tune_load_locked() {
     std::string line;
     while (std::getline(f, line)) {
         std::istringstream is(line);
-        int p, d, l0, l1, l2, l3, ls, spb, xcd;
-        if (is >> p >> d >> l0 >> l1 >> l2 >> l3 >> ls >> spb >> xcd) {
+        int p, d, l0, l1, l2, l3, ls, spb, xcd, spl;
+        if (is >> p >> d >> l0 >> l1 >> l2 >> l3 >> ls >> spb >> xcd >> spl) {
             std::ostringstream k;
             k << p << ' ' << d << ' ' << l0 << ' ' << l1 << ' ' << l2 << ' ' << l3 << ' ' << ls;
             DhopShape s;
             s.spb = spb;
             s.xcd = xcd;
+            s.nt_store = spl;
             g_tune[k.str()] = s;
         }
     }
@@ -107,7 +108,7 @@ int dwf_create(const dwf_geom *geom, dwf_ctx *out) {
     CHECK(std::isfinite(geom->M5) && std::isfinite(geom->mf), "dwf_create: M5 and mf must be finite");
     CHECK(std::fabs(5.0 - geom->M5) > 1e-12, "dwf_create: M5 = 5 makes M5op singular");
     const long vol = (long)geom->dims[0] * geom->dims[1] * geom->dims[2] * geom->dims[3];
-    CHECK(vol / 2 * geom->Ls * 24 < (1L << 40), "dwf_create: lattice too large");
+    CHECK(vol / 2 < (1L << 24), "dwf_create: lattice too large (V/2 must be below 2^24 sites)");
     dwf_ctx c = new (std::nothrow) dwf_ctx_s();
     if (!c) return fail(DWF_ENOMEM, "dwf_create: out of host memory");
     for (int m = 0; m < 4; ++m) c->g.L[m] = geom->dims[m];
@@ -406,13 +407,16 @@ int dwf_tune(dwf_ctx ctx, int prec, int dagger, double *best_us, void *stream) {
     }
     DWF_HIP(hipMemsetAsync(in, 0, cb, st));
     std::vector<DhopShape> cand;
-    for (int threads : {64, 128, 192, 256, 320, 384, 512, 768, 1024}) {
-        if (threads % ctx->g.Ls) continue;
-        for (int xcd : {0, 1}) {
-            DhopShape s;
-            s.spb = threads / ctx->g.Ls;
-            s.xcd = xcd;
-            cand.push_back(s);
+    for (int nt : {0, 1}) {
+        for (int threads : {64, 128, 192, 256, 320, 384, 448, 512}) {
+            if (threads % ctx->g.Ls) continue;
+            for (int xcd : {0, 1}) {
+                DhopShape s;
+                s.spb = threads / ctx->g.Ls;
+                s.xcd = xcd;
+                s.nt_store = nt;
+                cand.push_back(s);
+            }
         }
     }
     if (cand.empty()) {
@@ -439,6 +443,9 @@ int dwf_tune(dwf_ctx ctx, int prec, int dagger, double *best_us, void *stream) {
         float ms = 0;
         DWF_HIP(hipEventElapsedTime(&ms, e0, e1));
         const double us = 1000.0 * ms / reps;
+        if (std::getenv("DWF_LOG"))
+            std::fprintf(stderr, "[dwf] tune prec=%d dagger=%d nt=%d spb=%d threads=%d xcd=%d: %.2f us\n", prec, dagger,
+                         s.nt_store, s.spb, s.spb * ctx->g.Ls, s.xcd, us);
         if (us < best) {
             best = us;
             best_s = s;
@@ -455,7 +462,8 @@ int dwf_tune(dwf_ctx ctx, int prec, int dagger, double *best_us, void *stream) {
         g_tune[tune_key(ctx->g, prec, dagger)] = best_s;
         if (const char *path = std::getenv("DWF_TUNE_CACHE")) {
             std::ofstream f(path, std::ios::trunc);
-            for (auto &kv : g_tune) f << kv.first << ' ' << kv.second.spb << ' ' << kv.second.xcd << '\n';
+            for (auto &kv : g_tune)
+                f << kv.first << ' ' << kv.second.spb << ' ' << kv.second.xcd << ' ' << kv.second.nt_store << '\n';
         }
     }
     if (best_us) *best_us = best;

@@ -23,7 +23,8 @@ struct BatchLat {
     long half;
     long item_begin;  // first item of this lattice
     long tiles;
-    int L0h, L1, L2, L3, Ls, spb, nrhs, rhs_off;
+    Lat lat;
+    int Ls, spb, nrhs, rhs_off;
 };
 
 struct BatchDesc {
@@ -37,7 +38,7 @@ struct BatchDesc {
 };
 
 template <int P, int DAG>
-__global__ void __launch_bounds__(1024) k_dhop_batch(const BatchDesc *__restrict__ d) {
+__global__ void __launch_bounds__(kMaxDhopThreads) k_dhop_batch(const BatchDesc *__restrict__ d) {
     using A = typename PT<P>::A;
     const long lb = xcd_remap(blockIdx.x, gridDim.x);
     const long begin = lb * d->per_block;
@@ -58,8 +59,9 @@ __global__ void __launch_bounds__(1024) k_dhop_batch(const BatchDesc *__restrict
         A acc[24];
 #pragma unroll
         for (int k = 0; k < 24; ++k) acc[k] = 0;
-        dhop_site<P, DAG>(L.links, d->ins[L.rhs_off + rhs], L.L0h, L.L1, L.L2, L.L3, Ls, d->parity, c, s, acc);
-        store_spinor<P>(d->outs[L.rhs_off + rhs], c, Ls, s, acc);
+        dhop_site<P, DAG, long>((const char *)L.links, (const char *)d->ins[L.rhs_off + rhs], L.lat, Ls, d->parity,
+                                c, s, acc);
+        store_spinor_off<P>((char *)d->outs[L.rhs_off + rhs], spinor_off<P, long>(c, Ls, s), Ls * 16, acc, true);
     }
 }
 
@@ -99,7 +101,8 @@ int batch_plan(const dwf_ctx *ctxs, int nlat, const int *nrhs, int prec, int dag
     for (int l = 0; l < nlat; ++l) {
         const Geom &g = ctxs[l]->g;
         const DhopShape &sh = ctxs[l]->shape[prec][dagger];
-        const int spb = sh.spb > 0 ? sh.spb : default_shape(g).spb;
+        int spb = sh.spb > 0 ? sh.spb : default_shape(g).spb;
+        while (spb > 1 && spb * g.Ls > kMaxDhopThreads) --spb;
         if (spb * g.Ls > threads) threads = spb * g.Ls;
     }
     long items = 0;
@@ -109,10 +112,7 @@ int batch_plan(const dwf_ctx *ctxs, int nlat, const int *nrhs, int prec, int dag
         BatchLat &L = p->host.lat[l];
         L.links = ctxs[l]->links[prec][0];
         L.half = g.half;
-        L.L0h = g.L[0] / 2;
-        L.L1 = g.L[1];
-        L.L2 = g.L[2];
-        L.L3 = g.L[3];
+        L.lat = make_lat(g.L);
         L.Ls = g.Ls;
         L.spb = threads / g.Ls;
         L.tiles = (g.half + L.spb - 1) / L.spb;

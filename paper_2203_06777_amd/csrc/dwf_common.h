@@ -59,7 +59,10 @@ inline size_t link_bytes(const Geom &g, int prec) { return (size_t)g.half * 8 * 
 struct DhopShape {
     int spb = 0;        // 4D sites per workgroup (workgroup = spb * Ls lanes)
     int xcd = 1;        // XCD-aware block remap on/off
+    int nt_store = 1;   // non-temporal stores of the output (it is not re-read by this launch)
 };
+
+constexpr int kMaxDhopThreads = 512;
 
 // Epilogue modes of the hopping kernel (out is at the output parity):
 enum Epi {
