@@ -1,15 +1,17 @@
-"""Benchmark of the domain-wall hopping term on one MI355X.
+"""Benchmark of the domain-wall fermion hot path on one MI355X.
 
-Headline: checkerboarded Dhop at 32^4 x Ls=16 in FP32 (inputs resident in HBM).
-One step = one apply in each direction (D^{o<-e} then D^{e<-o}).  Flops are
-1320 * Ls per output 4D site per apply; the byte model counts 8 links of 18
-reals plus Ls input and Ls output spinors of 24 reals per output 4D site.
+Headline (the metric's workload): checkerboarded Dhop at 32^4 x Ls=16 in FP32,
+inputs resident in HBM.  One step = one apply in each direction
+(D^{o<-e} then D^{e<-o}).  Flops are 1320 * Ls per output 4D site per apply;
+the byte model counts 8 links of 18 reals plus Ls input and Ls output spinors
+of 24 reals per output 4D site.
 
-Also measured in the same run and reported under "rows": FP64 and 16-bit
-Dhop, the Schur normal operator, FP64 vs mixed-precision CG at 24^4 x 12
-(time to the FP64 solution), the batched multi-RHS / multi-lattice graph
-launch, and the force kernel.  The CPU oracle (plain C, OpenMP) is timed on a
-bounded sample of the headline workload.
+The other rows of the hot path are measured in the same run and reported
+under "rows": FP64 / FP16 / BF16 Dhop, the M5op family, the Schur normal
+operator, the FP64 reductions, FP64 vs mixed-precision CG at 24^4 x 12 (time
+to the FP64 solution), the batched graph launches, and the force kernel /
+differentiable action at 16^4 x 8.  The CPU oracle (plain C, OpenMP) is timed
+on a bounded sample of the headline workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--rows all|none|name,...] [--no-cpu]
 """
@@ -17,6 +19,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--rows all|none|name
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,6 +31,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2203_06777_amd/csrc/dhop.hip", "paper_2203_06777_amd/csrc/dwf_dhop_core.h",
+                  "paper_2203_06777_amd/csrc/dwf_device.h", "paper_2203_06777_amd/csrc/dwf_spin.h"]
 
 
 def log(msg):
@@ -42,14 +47,25 @@ def dhop_bytes(vol, ls, real_bytes, nrhs=1):
     return (8 * 18 + nrhs * ls * 48) * real_bytes * (vol // 2)
 
 
-def timed(fn, reps, torch):
-    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    s.record()
-    for _ in range(reps):
-        fn()
-    e.record()
-    e.synchronize()
-    return s.elapsed_time(e) / reps  # ms
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed counter summary, if it was taken on this kernel source."""
+    path = os.path.join(ROOT, "profiles", "dhop_32x32x32x32_ls16_f32_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None, None
+    if rec.get("src_sha") != kernel_source_sha():
+        return None, rec.get("src_sha")
+    return rec.get("bytes_per_launch"), rec.get("src_sha")
 
 
 def main():
@@ -79,6 +95,15 @@ def main():
     def row_on(name):
         return want_rows is None or name in want_rows
 
+    def timed(fn, reps):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        e.synchronize()
+        return s.elapsed_time(e) / reps  # ms
+
     # ---------------- headline: Dhop 32^4 x 16 FP32 ----------------
     w = F.WORKLOADS["dhop_32^4x16"]
     dims, ls = w["dims"], w["ls"]
@@ -90,9 +115,8 @@ def main():
     op = D.Context(dims, ls, w["M5"], w["mf"])
     op.set_gauge(torch.from_numpy(u).cuda())
     psi_d = torch.from_numpy(psi).cuda()
-    fin = {p: (op.pack(psi_d, 0, p), op.pack(psi_d, 1, p)) for p in ("f32",)}
-    fout = {p: (op.field(p), op.field(p)) for p in ("f32",)}
-    del psi_d
+    fin = {"f32": (op.pack(psi_d, 0, "f32"), op.pack(psi_d, 1, "f32"))}
+    fout = {"f32": (op.field("f32"), op.field("f32"))}
     torch.cuda.synchronize()
 
     def step(prec="f32"):
@@ -105,7 +129,6 @@ def main():
         step()
     torch.cuda.synchronize()
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     start.record()
     for _ in range(args.steps):
         step()
@@ -129,53 +152,66 @@ def main():
     parity_err = float(np.linalg.norm(got - want) / np.linalg.norm(want))
     log(f"sampled parity rel-L2 {parity_err:.2e}")
 
-    # ---------------- plain copy of known size (bandwidth and counter calibration) ----------------
+    # ---------------- plain copy of known size (bandwidth reference) ----------------
     nbytes = 1 << 30
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
     for _ in range(3):
         dst.copy_(src)
-    copy_ms = timed(lambda: dst.copy_(src), 10, torch)
+    copy_ms = timed(lambda: dst.copy_(src), 10)
     copy_gbs = 2 * nbytes / (copy_ms * 1e-3) / 1e9
     log(f"copy 1 GiB -> 1 GiB: {copy_ms * 1e3:.1f} us, {copy_gbs:.0f} GB/s (read+write)")
     del src, dst
     torch.cuda.empty_cache()
 
-    # ---------------- secondary rows ----------------
+    # ---------------- a1: Dhop in the other precisions ----------------
     def dhop_row(prec, rb):
-        fin[prec] = (op.pack(torch.from_numpy(psi).cuda(), 0, prec), op.pack(torch.from_numpy(psi).cuda(), 1, prec))
+        fin[prec] = (op.pack(psi_d, 0, prec), op.pack(psi_d, 1, prec))
         fout[prec] = (op.field(prec), op.field(prec))
         for _ in range(3):
             step(prec)
-        ms = timed(lambda: step(prec), 20, torch) / 2
+        ms = timed(lambda: step(prec), 20) / 2
+        got = op.unpack(fout[prec][1], 1, prec)[torch.from_numpy(rows_s).cuda()].cpu().numpy()
+        err = float(np.linalg.norm(got - want) / np.linalg.norm(want))
         del fin[prec], fout[prec]
         torch.cuda.empty_cache()
-        return {"us_per_apply": ms * 1e3, "gflops": flops / (ms * 1e-3) / 1e9,
-                "gbs": dhop_bytes(vol, ls, rb) / (ms * 1e-3) / 1e9,
-                "frac_hbm": dhop_bytes(vol, ls, rb) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        gbs = dhop_bytes(vol, ls, rb) / (ms * 1e-3) / 1e9
+        return {"us_per_apply": round(ms * 1e3, 1), "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
+                "gbs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "rel_l2_vs_oracle": err}
 
     for prec, rb in (("f64", 8), ("f16", 2), ("bf16", 2)):
-        if row_on(f"dhop_32^4x16_{prec}"):
-            rows[f"dhop_32^4x16_{prec}"] = dhop_row(prec, rb)
-            log(f"row dhop {prec}: {rows[f'dhop_32^4x16_{prec}']}")
+        name = f"dhop_32^4x16_{prec}"
+        if row_on(name):
+            rows[name] = dhop_row(prec, rb)
+            log(f"row {name}: {rows[name]}")
 
-    if row_on("mdagm_32^4x16_f32"):
-        pin = op.pack(torch.from_numpy(psi).cuda(), 1, "f32")
-        out = op.field("f32")
-        for _ in range(3):
-            D.dwf_mdagm(op.handle, out, pin, "f32")
-        ms = timed(lambda: D.dwf_mdagm(op.handle, out, pin, "f32"), 10, torch)
-        rows["mdagm_32^4x16_f32"] = {"ms": ms, "dhop_gflops": 4 * flops / (ms * 1e-3) / 1e9}
-        log(f"row mdagm: {rows['mdagm_32^4x16_f32']}")
-        del pin, out
+    # ---------------- a2/a3/a4 at the headline shape, FP32 ----------------
+    if row_on("m5_mdagm_blas_32^4x16_f32"):
+        x = fin["f32"][1]
+        y = op.field("f32")
+        cbb = dhop_bytes(vol, ls, 4) - 8 * 18 * 4 * (vol // 2)  # one field in + one out
+        r = {}
+        for nm, dag, inv in (("m5", 0, 0), ("m5inv", 0, 1), ("m5inv_dag", 1, 1)):
+            ms = timed(lambda: D.dwf_m5(op.handle, y, x, dag, inv, 0, "f32"), 20)
+            r[nm] = {"us": round(ms * 1e3, 1), "gbs": round(cbb / (ms * 1e-3) / 1e9, 1)}
+        ms = timed(lambda: D.dwf_mdagm(op.handle, y, x, "f32"), 10)
+        r["mdagm"] = {"ms": round(ms, 3), "dhop_gflops": round(4 * flops / (ms * 1e-3) / 1e9, 1)}
+        ms = timed(lambda: D.dwf_norm2(op.handle, x, 0, "f32"), 20)
+        r["norm2_sync"] = {"us": round(ms * 1e3, 1), "gbs": round(cbb / 2 / (ms * 1e-3) / 1e9, 1)}
+        ms = timed(lambda: D.dwf_axpy(op.handle, y, 0.5, x, 0, "f32"), 20)
+        r["axpy"] = {"us": round(ms * 1e3, 1), "gbs": round(1.5 * cbb / (ms * 1e-3) / 1e9, 1)}
+        rows["m5_mdagm_blas_32^4x16_f32"] = r
+        log(f"row m5/mdagm/blas: {r}")
+        del y
+    del psi_d, fin, fout
+    torch.cuda.empty_cache()
 
-    # ---------------- CPU oracle baseline ----------------
+    # ---------------- CPU oracle baseline (bounded sample of the headline workload) ----------------
     cpu = None
     if not args.no_cpu:
         from oracle import coracle as C
 
         nthreads = C.num_threads()
-        # size the sample from a short probe so the run stays within ~cpu-seconds
         probe = 512
         t = time.time()
         C.dhop_cb(u, psi, 1, 0, rows=(0, probe))
@@ -184,11 +220,143 @@ def main():
         t = time.time()
         C.dhop_cb(u, psi, 1, 0, rows=(0, nrow))
         dt = time.time() - t
-        cpu = {"value": 1320.0 * ls * nrow / dt / 1e9, "unit": "GFlop/s", "cores": nthreads, "kind": "oracle",
-               "sample": f"plain C FP64 Dhop_cb on the 32^4x16 input, first {nrow} of {vol // 2} output rows "
-                         f"({dt:.1f} s)"}
+        cpu = {"value": round(1320.0 * ls * nrow / dt / 1e9, 3), "unit": "GFlop/s", "cores": nthreads,
+               "kind": "oracle",
+               "sample": f"plain C FP64 Dhop_cb (oracle) on the 32^4x16 input, output rows 0..{nrow} of "
+                         f"{vol // 2} ({dt:.1f} s)"}
         log(f"cpu oracle: {cpu}")
+    op.close()
+    del u, psi
 
+    # ---------------- a5/a6: FP64 vs mixed CG at 24^4 x 12 ----------------
+    if row_on("cg_24^4x12"):
+        w = F.WORKLOADS["cg_24^4x12"]
+        cdims, cls = w["dims"], w["ls"]
+        u2 = F.gauge_field(cdims, w["eps"], w["seed_u"])
+        b = F.fermion_cb(cdims, cls, w["seed_psi"])
+        op2 = D.Context(cdims, cls, w["M5"], w["mf"])
+        op2.set_gauge(torch.from_numpy(u2).cuda())
+        bi = op2.pack(torch.from_numpy(b).cuda(), 1, "f64")
+        sol = {}
+        r = {}
+        for mode, nm in ((0, "fp64"), (1, "mixed_fp32"), (2, "mixed_fp16"), (3, "mixed_bf16")):
+            x = op2.zeros("f64")
+            torch.cuda.synchronize()
+            t = time.time()
+            st = D.dwf_cg(op2.handle, x, bi, w["tol"], 50000, mode)
+            torch.cuda.synchronize()
+            wall = time.time() - t
+            sol[mode] = x
+            r[nm] = {"seconds": round(wall, 4), "iters": st["inner_iters"], "outer": st["outer_iters"],
+                     "true_rel_resid": st["true_rel_resid"]}
+        nref = D.dwf_norm2(op2.handle, sol[0], 0, "f64")
+        for mode, nm in ((1, "mixed_fp32"), (2, "mixed_fp16"), (3, "mixed_bf16")):
+            d = op2.field("f64")
+            d.copy_(sol[mode])
+            D.dwf_axpy(op2.handle, d, -1.0, sol[0], 0, "f64")
+            r[nm]["rel_l2_vs_fp64"] = float(np.sqrt(D.dwf_norm2(op2.handle, d, 0, "f64") / nref))
+            r[nm]["speedup_vs_fp64"] = round(r["fp64"]["seconds"] / r[nm]["seconds"], 3)
+        rows["cg_24^4x12"] = r
+        log(f"row cg: {r}")
+        op2.close()
+        del sol, bi, u2, b
+        torch.cuda.empty_cache()
+
+    # ---------------- a7: batched graph launches ----------------
+    if row_on("batched"):
+        r = {}
+        g = torch.Generator(device="cuda").manual_seed(2040)
+        w = F.WORKLOADS["batch_32^4x12x12"]
+        bdims, bls = w["dims"], w["ls"]
+        op3 = D.Context(bdims, bls, w["M5"], w["mf"])
+        op3.set_gauge(torch.from_numpy(F.gauge_field(bdims, w["eps"], w["seed_u"])).cuda())
+        nr = len(w["rhs_seeds"])
+        ins, outs = [], []
+        for _ in range(nr):
+            p = torch.randn((vol // 2, bls, 4, 3), dtype=torch.complex128, device="cuda", generator=g)
+            ins.append(op3.pack(p, 1, "f32"))
+            outs.append(op3.field("f32"))
+            del p
+        plan = D.dwf_batch_plan([op3.handle], [nr], "f32", 0)
+        D.dwf_batch_capture(plan, outs, ins, 0)
+        for _ in range(2):
+            D.dwf_batch_launch(plan)
+        ms = timed(lambda: D.dwf_batch_launch(plan), 5)
+        ms1 = timed(lambda: [D.dwf_dhop(op3.handle, outs[k], ins[k], 0, 0, "f32") for k in range(nr)], 3)
+        fl = dhop_flops(vol, bls, nr)
+        by = dhop_bytes(vol, bls, 4, nr)
+        r["32^4x12x12rhs"] = {"graph_ms": round(ms, 3), "gflops": round(fl / (ms * 1e-3) / 1e9, 1),
+                               "gbs": round(by / (ms * 1e-3) / 1e9, 1), "per_rhs_launches_ms": round(ms1, 3)}
+        D.dwf_batch_free(plan)
+        del ins, outs
+        op3.close()
+        torch.cuda.empty_cache()
+        wm = F.WORKLOADS["batch_mixed"]
+        ctxs, ins, outs, nrhs = [], [], [], []
+        fl = by = 0.0
+        for lat in wm["lattices"]:
+            ld, lls = lat["dims"], lat["ls"]
+            o = D.Context(ld, lls, wm["M5"], wm["mf"])
+            o.set_gauge(torch.from_numpy(F.gauge_field(ld, wm["eps"], lat["seed_u"])).cuda())
+            ctxs.append(o)
+            nrhs.append(len(lat["rhs_seeds"]))
+            v = int(np.prod(ld))
+            for _ in lat["rhs_seeds"]:
+                p = torch.randn((v // 2, lls, 4, 3), dtype=torch.complex128, device="cuda", generator=g)
+                ins.append(o.pack(p, 1, "f32"))
+                outs.append(o.field("f32"))
+            fl += dhop_flops(v, lls, nrhs[-1])
+            by += dhop_bytes(v, lls, 4, nrhs[-1])
+        plan = D.dwf_batch_plan([c.handle for c in ctxs], nrhs, "f32", 0)
+        D.dwf_batch_capture(plan, outs, ins, 0)
+        for _ in range(2):
+            D.dwf_batch_launch(plan)
+        ms = timed(lambda: D.dwf_batch_launch(plan), 20)
+
+        def singles():
+            k = 0
+            for li, o in enumerate(ctxs):
+                for _ in range(nrhs[li]):
+                    D.dwf_dhop(o.handle, outs[k], ins[k], 0, 0, "f32")
+                    k += 1
+
+        ms1 = timed(singles, 5)
+        r["mixed_8_12_16_20x8x4rhs"] = {"graph_ms": round(ms, 4), "gflops": round(fl / (ms * 1e-3) / 1e9, 1),
+                                         "gbs": round(by / (ms * 1e-3) / 1e9, 1), "per_rhs_launches_ms": round(ms1, 4)}
+        D.dwf_batch_free(plan)
+        for c in ctxs:
+            c.close()
+        del ins, outs
+        torch.cuda.empty_cache()
+        rows["batched_f32"] = r
+        log(f"row batched: {r}")
+
+    # ---------------- a8: force kernel and differentiable action at 16^4 x 8 ----------------
+    if row_on("force_16^4x8"):
+        from paper_2203_06777_amd.autograd import dwf_action
+
+        w = F.WORKLOADS["force_16^4x8"]
+        fdims, fls = w["dims"], w["ls"]
+        op4 = D.Context(fdims, fls, w["M5"], w["mf"])
+        U = torch.from_numpy(F.gauge_field(fdims, w["eps"], w["seed_u"])).cuda().requires_grad_(True)
+        phi = torch.from_numpy(F.fermion_full(fdims, fls, w["seed_phi"])).cuda()
+        torch.cuda.synchronize()
+        t = time.time()
+        s = dwf_action(op4, U, phi, 1e-10)
+        s.backward()
+        torch.cuda.synchronize()
+        wall = time.time() - t
+        X = op4.pack(phi, 2, "f64")
+        Fo = torch.empty_like(U)
+        ms = timed(lambda: D.dwf_force(op4.handle, Fo, X, X, 1, 1.0), 10)
+        fv = int(np.prod(fdims))
+        fbytes = fv * 4 * (4 * 24 * 8 * fls + 18 * 8 * 2)
+        rows["force_16^4x8"] = {"action_plus_grad_seconds": round(wall, 3), "force_kernel_us": round(ms * 1e3, 1),
+                                "force_kernel_gbs": round(fbytes / (ms * 1e-3) / 1e9, 1)}
+        log(f"row force: {rows['force_16^4x8']}")
+        op4.close()
+
+    traffic, sha = measured_traffic()
     out = {
         "metric": "DWF Dhop GFlop/s & HBM GB/s on 1 GPU; mixed vs FP64 CG time-to-1e-8",
         "value": round(gflops, 1),
@@ -205,9 +373,9 @@ def main():
         "config": {"workload": "dhop_cb 32^4 x Ls=16 FP32, one apply per parity per step", "dims": list(dims),
                    "Ls": ls, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_dhop<F32,F32,0,EPI_SCALE>", "algorithmic_bytes_per_launch": algo_bytes,
-                     "us_per_launch": round(apply_ms * 1e3, 2)},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "k_dhop_rows<F32,F32,0,EPI_SCALE,16>", "algorithmic_bytes_per_launch": algo_bytes,
+                     "us_per_launch": round(apply_ms * 1e3, 2), "kernel_src_sha": kernel_source_sha()},
         "parity_rel_l2_sampled": parity_err,
         "copy_gbs": round(copy_gbs, 1),
         "frac_of_copy": round(achieved / copy_gbs, 4),
@@ -215,7 +383,6 @@ def main():
         "rows": rows,
     }
     print(json.dumps(out), flush=True)
-    op.close()
 
 
 if __name__ == "__main__":

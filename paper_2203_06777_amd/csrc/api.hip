@@ -66,14 +66,18 @@ static void tune_load_locked() {
     std::string line;
     while (std::getline(f, line)) {
         std::istringstream is(line);
-        int p, d, l0, l1, l2, l3, ls, spb, xcd, spl;
-        if (is >> p >> d >> l0 >> l1 >> l2 >> l3 >> ls >> spb >> xcd >> spl) {
+        int p, d, l0, l1, l2, l3, ls, spb, xcd, spl, rows, ty, tz, tt;
+        if (is >> p >> d >> l0 >> l1 >> l2 >> l3 >> ls >> spb >> xcd >> spl >> rows >> ty >> tz >> tt) {
             std::ostringstream k;
             k << p << ' ' << d << ' ' << l0 << ' ' << l1 << ' ' << l2 << ' ' << l3 << ' ' << ls;
             DhopShape s;
             s.spb = spb;
             s.xcd = xcd;
             s.nt_store = spl;
+            s.rows = rows;
+            s.ty = ty;
+            s.tz = tz;
+            s.tt = tt;
             g_tune[k.str()] = s;
         }
     }
@@ -85,7 +89,7 @@ static void apply_tuned(dwf_ctx ctx) {
     for (int p = 0; p < 4; ++p)
         for (int d = 0; d < 2; ++d) {
             auto it = g_tune.find(tune_key(ctx->g, p, d));
-            ctx->shape[p][d] = it != g_tune.end() ? it->second : default_shape(ctx->g);
+            ctx->shape[p][d] = it != g_tune.end() ? it->second : default_row_shape(ctx->g, p, ctx->lds_limit);
         }
 }
 
@@ -123,6 +127,11 @@ int dwf_create(const dwf_geom *geom, dwf_ctx *out) {
         return fail(code, msg);
     };
     if (hipGetDevice(&c->device) != hipSuccess) return cleanup(DWF_EHIP, "dwf_create: no HIP device");
+    {
+        int lds = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) == hipSuccess && lds > 0)
+            c->lds_limit = (size_t)lds;
+    }
     if (std::getenv("DWF_TEST_FAIL_ALLOC")) return cleanup(DWF_ENOMEM, "dwf_create: allocation failure forced");
     for (int p = 0; p < 4; ++p)
         for (int par = 0; par < 2; ++par)
@@ -399,40 +408,87 @@ int dwf_tune(dwf_ctx ctx, int prec, int dagger, double *best_us, void *stream) {
     CHECK_GAUGE(ctx);
     CHECK(valid_prec(prec) && (dagger == 0 || dagger == 1), "dwf_tune: bad precision or dagger");
     hipStream_t st = (hipStream_t)stream;
-    const size_t cb = cb_bytes(ctx->g, prec);
-    void *in = nullptr, *out = nullptr;
-    if (hipMalloc(&in, cb) != hipSuccess || hipMalloc(&out, cb) != hipSuccess) {
+    const Geom &g = ctx->g;
+    const size_t cb = cb_bytes(g, prec);
+    void *in = nullptr, *out = nullptr, *ref = nullptr;
+    unsigned *ndiff = nullptr;
+    auto release = [&]() {
         hipFree(in);
+        hipFree(out);
+        hipFree(ref);
+        hipFree(ndiff);
+    };
+    if (hipMalloc(&in, cb) != hipSuccess || hipMalloc(&out, cb) != hipSuccess || hipMalloc(&ref, cb) != hipSuccess ||
+        hipMalloc((void **)&ndiff, sizeof(unsigned)) != hipSuccess) {
+        release();
         return fail(DWF_ENOMEM, "dwf_tune: scratch allocation failed");
     }
-    DWF_HIP(hipMemsetAsync(in, 0, cb, st));
+    int rc = launch_fill_pattern(in, cb, prec, st);
+    if (rc) {
+        release();
+        return rc;
+    }
+    // candidates: site kernel (workgroup sizes x XCD remap x store kind), row kernel (rows x tiles x remap)
     std::vector<DhopShape> cand;
-    for (int nt : {0, 1}) {
+    for (int nt : {0, 1})
         for (int threads : {64, 128, 192, 256, 320, 384, 448, 512}) {
-            if (threads % ctx->g.Ls) continue;
+            if (threads % g.Ls) continue;
             for (int xcd : {0, 1}) {
                 DhopShape s;
-                s.spb = threads / ctx->g.Ls;
+                s.spb = threads / g.Ls;
                 s.xcd = xcd;
                 s.nt_store = nt;
                 cand.push_back(s);
             }
         }
+    {
+        const int per_row = (g.L[0] / 2) * g.Ls;
+        const int tiles[][3] = {{1, 1, 1}, {4, 4, g.L[3]}, {8, 8, g.L[3]}, {4, 4, 8}, {g.L[1], 1, 1}, {2, 2, g.L[3]}};
+        for (int rows = 1; rows * per_row <= kMaxDhopThreads; ++rows)
+            for (const auto &tl : tiles)
+                for (int xcd : {0, 1}) {
+                    DhopShape s;
+                    s.rows = rows;
+                    s.ty = tl[0];
+                    s.tz = tl[1];
+                    s.tt = tl[2];
+                    s.xcd = xcd;
+                    s.nt_store = 1;
+                    if (row_shape_ok(g, s, prec, ctx->lds_limit)) cand.push_back(s);
+                }
     }
-    if (cand.empty()) {
-        DhopShape s = default_shape(ctx->g);
-        cand.push_back(s);
-    }
+    if (cand.empty()) cand.push_back(default_shape(g));
     hipEvent_t e0, e1;
     DWF_HIP(hipEventCreate(&e0));
     DWF_HIP(hipEventCreate(&e1));
     double best = 1e30;
     DhopShape best_s = cand[0];
     const int reps = 10;
+    bool have_ref = false;
+    int status = DWF_OK;
     for (const DhopShape &s : cand) {
+        // every shape must reproduce the first one's output bit for bit
         DhopCall c{in, out, nullptr, 1, dagger, EPI_SCALE, 1.0, 0.0, prec, prec};
-        int rc = launch_dhop(ctx, c, s, st);  // warm-up
-        if (rc) continue;
+        if ((rc = launch_dhop(ctx, c, s, st))) continue;
+        if (!have_ref) {
+            DWF_HIP(hipMemcpyAsync(ref, out, cb, hipMemcpyDeviceToDevice, st));
+            have_ref = true;
+        } else {
+            DWF_HIP(hipMemsetAsync(ndiff, 0, sizeof(unsigned), st));
+            if ((rc = launch_count_diff(out, ref, cb, ndiff, st))) {
+                status = rc;
+                break;
+            }
+            unsigned h = 0;
+            DWF_HIP(hipMemcpyAsync(&h, ndiff, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+            DWF_HIP(hipStreamSynchronize(st));
+            if (h != 0) {
+                status = fail(DWF_EHIP, "dwf_tune: a launch shape changed the result (" + std::to_string(h) +
+                                            " vectors differ): rows=" + std::to_string(s.rows) +
+                                            " spb=" + std::to_string(s.spb));
+                break;
+            }
+        }
         DWF_HIP(hipEventRecord(e0, st));
         for (int r = 0; r < reps; ++r) {
             c.out_parity = r & 1;
@@ -444,8 +500,8 @@ int dwf_tune(dwf_ctx ctx, int prec, int dagger, double *best_us, void *stream) {
         DWF_HIP(hipEventElapsedTime(&ms, e0, e1));
         const double us = 1000.0 * ms / reps;
         if (std::getenv("DWF_LOG"))
-            std::fprintf(stderr, "[dwf] tune prec=%d dagger=%d nt=%d spb=%d threads=%d xcd=%d: %.2f us\n", prec, dagger,
-                         s.nt_store, s.spb, s.spb * ctx->g.Ls, s.xcd, us);
+            std::fprintf(stderr, "[dwf] tune prec=%d dagger=%d nt=%d spb=%d rows=%d tile=%dx%dx%d xcd=%d: %.2f us\n",
+                         prec, dagger, s.nt_store, s.spb, s.rows, s.ty, s.tz, s.tt, s.xcd, us);
         if (us < best) {
             best = us;
             best_s = s;
@@ -453,8 +509,9 @@ int dwf_tune(dwf_ctx ctx, int prec, int dagger, double *best_us, void *stream) {
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    hipFree(in);
-    hipFree(out);
+    hipStreamSynchronize(st);
+    release();
+    if (status != DWF_OK) return status;
     ctx->shape[prec][dagger] = best_s;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -463,7 +520,8 @@ int dwf_tune(dwf_ctx ctx, int prec, int dagger, double *best_us, void *stream) {
         if (const char *path = std::getenv("DWF_TUNE_CACHE")) {
             std::ofstream f(path, std::ios::trunc);
             for (auto &kv : g_tune)
-                f << kv.first << ' ' << kv.second.spb << ' ' << kv.second.xcd << ' ' << kv.second.nt_store << '\n';
+                f << kv.first << ' ' << kv.second.spb << ' ' << kv.second.xcd << ' ' << kv.second.nt_store << ' '
+                  << kv.second.rows << ' ' << kv.second.ty << ' ' << kv.second.tz << ' ' << kv.second.tt << '\n';
         }
     }
     if (best_us) *best_us = best;

@@ -99,6 +99,54 @@ __global__ void __launch_bounds__(256) k_axpy(u32x4 *y, const u32x4 *x, double a
     y[v] = pack16<P>(yv);
 }
 
+// Deterministic finite pattern in [-1, 1] (used by the tuner to exercise every launch shape).
+template <int P>
+__global__ void __launch_bounds__(256) k_fill_pattern(u32x4 *f, long nv) {
+    constexpr int R = 2 * PT<P>::G;
+    using A = typename PT<P>::A;
+    const long v = (long)blockIdx.x * 256 + threadIdx.x;
+    if (v >= nv) return;
+    A vals[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        unsigned h = (unsigned)(v * R + k) * 2654435761u;
+        h ^= h >> 15;
+        vals[k] = (A)((int)(h % 2001u) - 1000) * (A)1e-3;
+    }
+    f[v] = pack16<P>(vals);
+}
+
+// Count 16-byte vectors that differ bitwise.
+__global__ void __launch_bounds__(256) k_count_diff(const u32x4 *a, const u32x4 *b, long nv, unsigned *count) {
+    const long v = (long)blockIdx.x * 256 + threadIdx.x;
+    if (v >= nv) return;
+    const u32x4 x = a[v], y = b[v];
+    const unsigned d = (x.x ^ y.x) | (x.y ^ y.y) | (x.z ^ y.z) | (x.w ^ y.w);
+    if (d) atomicAdd(count, 1u);
+}
+
+int launch_fill_pattern(void *f, size_t bytes, int prec, hipStream_t st) {
+    const long nv = (long)(bytes / 16);
+    const unsigned nb = (unsigned)((nv + 255) / 256);
+    u32x4 *fv = (u32x4 *)f;
+    switch (prec) {
+        case DWF_F64: hipLaunchKernelGGL(k_fill_pattern<DWF_F64>, nb, 256, 0, st, fv, nv); break;
+        case DWF_F32: hipLaunchKernelGGL(k_fill_pattern<DWF_F32>, nb, 256, 0, st, fv, nv); break;
+        case DWF_F16: hipLaunchKernelGGL(k_fill_pattern<DWF_F16>, nb, 256, 0, st, fv, nv); break;
+        default: hipLaunchKernelGGL(k_fill_pattern<DWF_BF16>, nb, 256, 0, st, fv, nv); break;
+    }
+    DWF_HIP(hipGetLastError());
+    return DWF_OK;
+}
+
+int launch_count_diff(const void *a, const void *b, size_t bytes, unsigned *count, hipStream_t st) {
+    const long nv = (long)(bytes / 16);
+    hipLaunchKernelGGL(k_count_diff, (unsigned)((nv + 255) / 256), 256, 0, st, (const u32x4 *)a, (const u32x4 *)b, nv,
+                       count);
+    DWF_HIP(hipGetLastError());
+    return DWF_OK;
+}
+
 static long nvec(long ncomplex, int prec) {
     const int g = prec == DWF_F64 ? 1 : prec == DWF_F32 ? 2 : 4;
     return ncomplex / g;

@@ -27,6 +27,10 @@ struct DhopArgs {
     Lat lat;
     long half;
     int Ls, spb, parity, xcd, nt_store;
+    // row kernel: rows per workgroup, number of rows, traversal tile and its reciprocals
+    int rows;
+    unsigned nrows, ty, tz, tt, nty, ntt;
+    float inv_per, inv_ty, inv_tz, inv_ntt, inv_ntyt;
     double alpha, beta, d5, mf;
     double coef[kMaxLs];
 };
@@ -56,9 +60,9 @@ __device__ __forceinline__ void m5inv_lds(const DhopArgs &a, int Ls, A *lds, int
         const A *vl = site + (DAG ? sm : sp) * 25;  // lower spins
         const A fu = DAG ? fp : fm, fl = DAG ? fm : fp;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) o[k] += fu * vu[k];
+        for (int k = 0; k < 12; ++k) o[k] = fma_(fu, vu[k], o[k]);
 #pragma unroll
-        for (int k = 12; k < 24; ++k) o[k] += fl * vl[k];
+        for (int k = 12; k < 24; ++k) o[k] = fma_(fl, vl[k], o[k]);
     }
 #pragma unroll
     for (int k = 0; k < 24; ++k) v[k] = o[k];
@@ -129,6 +133,207 @@ __global__ void __launch_bounds__(kMaxDhopThreads) k_dhop(const DhopArgs a) {
     store_spinor_off<PO>(a.out, spinor_off<PO, Off>(c, Ls, s), Ls * 16, acc, a.nt_store != 0);
 }
 
+
+// Physical row (x1 + L1 (x2 + L2 x3)) of logical row q: rows are visited tile by
+// tile, (ty, tz, tt) rows per tile with y fastest inside a tile, tiles with t
+// fastest, so a run of consecutive logical rows is a compact (y, z, t) block.
+__device__ __forceinline__ void rowmap(const DhopArgs &a, unsigned q, unsigned &x1, unsigned &x2, unsigned &x3) {
+    const unsigned per = a.ty * a.tz * a.tt;
+    const unsigned T = fdiv(q, per, a.inv_per);
+    const unsigned w = q - T * per;
+    const unsigned w1 = fdiv(w, a.ty, a.inv_ty);
+    const unsigned ly = w - w1 * a.ty;
+    const unsigned lt = fdiv(w1, a.tz, a.inv_tz);
+    const unsigned lz = w1 - lt * a.tz;
+    const unsigned T1 = fdiv(T, a.ntt, a.inv_ntt);  // T = Tt + ntt (Ty + nty Tz)
+    const unsigned Tt = T - T1 * a.ntt;
+    const unsigned Tz = fdiv(T1, a.nty, a.inv_ntyt);
+    const unsigned Ty = T1 - Tz * a.nty;
+    x1 = Ty * a.ty + ly;
+    x2 = Tz * a.tz + lz;
+    x3 = Tt * a.tt + lt;
+}
+
+// Row kernel: a workgroup owns `rows` whole x-rows (L0h sites x Ls slices each).
+// The rows' 8 L0h links and the input rows at the same (y, z, t) (which hold
+// both x-neighbours of every output site) are first copied to LDS with
+// contiguous 16-byte loads; the x-hops and every link then come from LDS and
+// only the y, z and t neighbours are read from global memory.
+template <int PI, int PO, int DAG, int EPI, int LS>
+__global__ void __launch_bounds__(kMaxDhopThreads) k_dhop_rows(const DhopArgs a) {
+    using A = typename PT<PI>::A;
+    using Off = typename std::conditional<(LS > 0), unsigned, long>::type;
+    constexpr int G = PT<PI>::G, NG = 12 / G, R2 = 2 * G;
+    constexpr int LREC = sizeof(A) == 8 ? 18 : 20;  // 16-byte aligned link records in LDS
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int Ls = LS > 0 ? LS : a.Ls;
+    const int L0h = (int)a.lat.L0h;
+    const int per_row = L0h * Ls;
+    const int nthr = a.rows * per_row;
+    const int t = threadIdx.x;
+    const int r = t / per_row;
+    const int wi = t - r * per_row;
+    const int xh = wi / Ls;
+    const int s = wi - xh * Ls;
+    const long lb = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (long)blockIdx.x;
+    const unsigned q0 = (unsigned)lb * (unsigned)a.rows;
+
+    A *lds_link = reinterpret_cast<A *>(smem);
+    const int link_reals = L0h * 8 * LREC;  // per row
+    u32x4 *lds_x = reinterpret_cast<u32x4 *>(smem + (size_t)a.rows * link_reals * sizeof(A));
+    const int VX = L0h * NG * Ls;                       // 16-byte vectors per field row
+    const int VL = L0h * 8 * 18 * PT<PI>::RB / 16;      // 16-byte vectors of links per row
+    for (int v = t; v < a.rows * VL; v += nthr) {
+        const int rr = v / VL, within = v - rr * VL;
+        if (q0 + rr >= a.nrows) continue;
+        unsigned y1, y2, y3;
+        rowmap(a, q0 + rr, y1, y2, y3);
+        const long prow = y1 + (long)a.lat.L1 * (y2 + (long)a.lat.L2 * y3);
+        const u32x4 raw = *(const u32x4 *)(a.links + (prow * VL + within) * 16);
+        A vals[R2];
+        unpack16<PI>(raw, vals);
+#pragma unroll
+        for (int e = 0; e < R2; ++e) {
+            const int idx = within * R2 + e;  // real index inside the row's link block
+            const int site = idx / 144, rem = idx - site * 144;
+            const int dir = rem / 18, k = rem - dir * 18;
+            lds_link[(rr * L0h + site) * 8 * LREC + dir * LREC + k] = vals[e];
+        }
+    }
+    for (int v = t; v < a.rows * VX; v += nthr) {
+        const int rr = v / VX, within = v - rr * VX;
+        if (q0 + rr >= a.nrows) continue;
+        unsigned y1, y2, y3;
+        rowmap(a, q0 + rr, y1, y2, y3);
+        const long prow = y1 + (long)a.lat.L1 * (y2 + (long)a.lat.L2 * y3);
+        lds_x[v] = *(const u32x4 *)(a.in + (prow * VX + within) * 16);
+    }
+    __syncthreads();
+
+    const bool active = q0 + r < a.nrows;
+    unsigned x1 = 0, x2 = 0, x3 = 0;
+    if (active) rowmap(a, q0 + r, x1, x2, x3);
+    const long rest = x1 + (long)a.lat.L1 * (x2 + (long)a.lat.L2 * x3);
+    const long c = rest * L0h + xh;
+    A acc[24];
+#pragma unroll
+    for (int k = 0; k < 24; ++k) acc[k] = 0;
+    if (active) {
+        const unsigned L0 = 2 * a.lat.L0h, L1 = a.lat.L1, L2 = a.lat.L2, L3 = a.lat.L3;
+        const unsigned x0 = 2 * xh + ((a.parity + x1 + x2 + x3) & 1);
+        const int lx0 = (int)((x0 + 1 == L0 ? 0 : x0 + 1) >> 1);
+        const int lx4 = (int)((x0 == 0 ? L0 - 1 : x0 - 1) >> 1);
+        const long s2 = L1, s3 = (long)L1 * L2;
+        const long nb1 = (rest + (x1 + 1 == L1 ? -(long)(L1 - 1) : 1)) * L0h + xh;
+        const long nb5 = (rest + (x1 == 0 ? (long)(L1 - 1) : -1)) * L0h + xh;
+        const long nb2 = (rest + (x2 + 1 == L2 ? -(long)(L2 - 1) * s2 : s2)) * L0h + xh;
+        const long nb6 = (rest + (x2 == 0 ? (long)(L2 - 1) * s2 : -s2)) * L0h + xh;
+        const long nb3 = (rest + (x3 + 1 == L3 ? -(long)(L3 - 1) * s3 : s3)) * L0h + xh;
+        const long nb7 = (rest + (x3 == 0 ? (long)(L3 - 1) * s3 : -s3)) * L0h + xh;
+        const A *lk = lds_link + (r * L0h + xh) * 8 * LREC;
+        const u32x4 *xr = lds_x + r * VX;
+        constexpr int SG = DAG ? 1 : -1;
+#define DWF_HOP_LDS(DIR, MU, TAU, LX)                                                        \
+    {                                                                                        \
+        A w[18], p[24], h[12];                                                               \
+        _Pragma("unroll") for (int k = 0; k < 18; ++k) w[k] = lk[DIR * LREC + k];            \
+        _Pragma("unroll") for (int g = 0; g < NG; ++g) unpack16<PI>(xr[((LX)*NG + g) * Ls + s], p + R2 * g); \
+        project<MU, TAU>(p, h);                                                              \
+        mul_reconstruct<MU, TAU>(w, h, acc);                                                 \
+    }
+#define DWF_HOP_GLB(DIR, MU, TAU, NB)                                                        \
+    {                                                                                        \
+        A w[18], p[24], h[12];                                                               \
+        _Pragma("unroll") for (int k = 0; k < 18; ++k) w[k] = lk[DIR * LREC + k];            \
+        load_spinor_off<PI>(a.in, spinor_off<PI, Off>(NB, Ls, s), Ls * 16, p);               \
+        project<MU, TAU>(p, h);                                                              \
+        mul_reconstruct<MU, TAU>(w, h, acc);                                                 \
+    }
+        DWF_HOP_LDS(0, 0, SG, lx0)
+        DWF_HOP_GLB(1, 1, SG, nb1)
+        DWF_HOP_GLB(2, 2, SG, nb2)
+        DWF_HOP_GLB(3, 3, SG, nb3)
+        DWF_HOP_LDS(4, 0, -SG, lx4)
+        DWF_HOP_GLB(5, 1, -SG, nb5)
+        DWF_HOP_GLB(6, 2, -SG, nb6)
+        DWF_HOP_GLB(7, 3, -SG, nb7)
+#undef DWF_HOP_LDS
+#undef DWF_HOP_GLB
+    }
+
+    const A alpha = (A)a.alpha;
+    const Off zoff = spinor_off<PI, Off>(c, Ls, s);
+    if constexpr (EPI == EPI_SCALE) {
+        if (!active) return;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) acc[k] *= alpha;
+    } else if constexpr (EPI == EPI_AXPY) {
+        if (!active) return;
+        A zv[24];
+        load_spinor_off<PI>(a.z, zoff, Ls * 16, zv);
+        const A beta = (A)a.beta;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) acc[k] = beta * zv[k] + alpha * acc[k];
+    } else if constexpr (EPI == EPI_M5) {
+        if (!active) return;
+        A z0[24], zu[24], zd[24];
+        const Off row = zoff - (Off)(s * 16);
+        load_spinor_off<PI>(a.z, zoff, Ls * 16, z0);
+        load_spinor_off<PI>(a.z, row + (Off)((s + 1 < Ls ? s + 1 : 0) * 16), Ls * 16, zu);
+        load_spinor_off<PI>(a.z, row + (Off)((s >= 1 ? s - 1 : Ls - 1) * 16), Ls * 16, zd);
+        const A fu = s + 1 < Ls ? (A)1 : (A)(-a.mf);
+        const A fd = s >= 1 ? (A)1 : (A)(-a.mf);
+        const A d5 = (A)a.d5;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = d5 * z0[k] - (DAG ? fu * zu[k] : fd * zd[k]) + alpha * acc[k];
+#pragma unroll
+        for (int k = 12; k < 24; ++k) acc[k] = d5 * z0[k] - (DAG ? fd * zd[k] : fu * zu[k]) + alpha * acc[k];
+    } else {  // EPI_M5INV: the LDS staging area is reused once every lane is done with it
+        A *lds = reinterpret_cast<A *>(smem);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) acc[k] *= alpha;
+        if (a.z != nullptr && active) {
+            A zv[24];
+            load_spinor_off<PI>(a.z, zoff, Ls * 16, zv);
+            const A beta = (A)a.beta;
+#pragma unroll
+            for (int k = 0; k < 24; ++k) acc[k] += beta * zv[k];
+        }
+        __syncthreads();
+        m5inv_lds<DAG>(a, Ls, lds, r * L0h + xh, s, acc);
+        if (!active) return;
+    }
+    store_spinor_off<PO>(a.out, spinor_off<PO, Off>(c, Ls, s), Ls * 16, acc, a.nt_store != 0);
+}
+
+size_t row_lds_bytes(int rows, int L0h, int Ls, int prec) {
+    const size_t areal = prec == DWF_F64 ? 8 : 4;
+    const size_t lrec = prec == DWF_F64 ? 18 : 20;
+    return (size_t)rows * ((size_t)L0h * 8 * lrec * areal + (size_t)L0h * Ls * 24 * real_bytes(prec));
+}
+
+bool row_shape_ok(const Geom &g, const DhopShape &sh, int prec, size_t lds_limit) {
+    if (sh.rows < 1) return false;
+    const int threads = sh.rows * (g.L[0] / 2) * g.Ls;
+    if (threads > kMaxDhopThreads) return false;
+    if (g.L[1] % sh.ty || g.L[2] % sh.tz || g.L[3] % sh.tt) return false;
+    size_t need = row_lds_bytes(sh.rows, g.L[0] / 2, g.Ls, prec);
+    need = std::max(need, (size_t)threads * 25 * (prec == DWF_F64 ? 8 : 4));
+    return need <= lds_limit;
+}
+
+DhopShape default_row_shape(const Geom &g, int prec, size_t lds_limit) {
+    DhopShape sh = default_shape(g);
+    const int per_row = (g.L[0] / 2) * g.Ls;
+    if (per_row > kMaxDhopThreads) return sh;
+    DhopShape r = sh;
+    r.rows = std::max(1, 256 / per_row);
+    r.ty = g.L[1] % 4 == 0 ? 4 : 1;
+    r.tz = g.L[2] % 4 == 0 ? 4 : 1;
+    r.tt = g.L[3];
+    return row_shape_ok(g, r, prec, lds_limit) ? r : sh;
+}
+
 DhopShape default_shape(const Geom &g) {
     DhopShape sh;
     int spb = 256 / g.Ls;
@@ -158,8 +363,20 @@ void m5inv_coefficients(const Geom &g, double *coef) {
 template <int PI, int PO, int DAG, int EPI>
 static int launch_t(const DhopArgs &a, int ls_t, long nblocks, int threads, hipStream_t st) {
     using A = typename PT<PI>::A;
-    const size_t shm = EPI == EPI_M5INV ? (size_t)a.spb * a.Ls * 25 * sizeof(A) : 0;
     const dim3 grid((unsigned)nblocks), block(threads);
+    if (a.rows > 0) {
+        const size_t shm = std::max(row_lds_bytes(a.rows, (int)a.lat.L0h, a.Ls, PI),
+                                    EPI == EPI_M5INV ? (size_t)threads * 25 * sizeof(A) : (size_t)0);
+        switch (ls_t) {
+            case 8: hipLaunchKernelGGL((k_dhop_rows<PI, PO, DAG, EPI, 8>), grid, block, shm, st, a); break;
+            case 12: hipLaunchKernelGGL((k_dhop_rows<PI, PO, DAG, EPI, 12>), grid, block, shm, st, a); break;
+            case 16: hipLaunchKernelGGL((k_dhop_rows<PI, PO, DAG, EPI, 16>), grid, block, shm, st, a); break;
+            default: hipLaunchKernelGGL((k_dhop_rows<PI, PO, DAG, EPI, 0>), grid, block, shm, st, a); break;
+        }
+        DWF_HIP(hipGetLastError());
+        return DWF_OK;
+    }
+    const size_t shm = EPI == EPI_M5INV ? (size_t)a.spb * a.Ls * 25 * sizeof(A) : 0;
     switch (ls_t) {
         case 8: hipLaunchKernelGGL((k_dhop<PI, PO, DAG, EPI, 8>), grid, block, shm, st, a); break;
         case 12: hipLaunchKernelGGL((k_dhop<PI, PO, DAG, EPI, 12>), grid, block, shm, st, a); break;
@@ -190,7 +407,7 @@ static int launch_pp(const DhopArgs &a, int ls_t, int dagger, int epi, long nb, 
 
 int launch_dhop(dwf_ctx ctx, const DhopCall &c, const DhopShape &shape_in, hipStream_t st) {
     const Geom &g = ctx->g;
-    DhopShape shape = shape_in.spb > 0 ? shape_in : default_shape(g);
+    DhopShape shape = (shape_in.spb > 0 || shape_in.rows > 0) ? shape_in : default_shape(g);
     DhopArgs a;
     a.in = (const char *)c.in;
     a.out = (char *)c.out;
@@ -208,9 +425,31 @@ int launch_dhop(dwf_ctx ctx, const DhopCall &c, const DhopShape &shape_in, hipSt
     a.d5 = 5.0 - g.M5;
     a.mf = g.mf;
     m5inv_coefficients(g, a.coef);
-    const int threads = shape.spb * g.Ls;
+    const bool rows_mode = shape.rows > 0 && row_shape_ok(g, shape, c.prec_in, ctx->lds_limit);
+    a.rows = rows_mode ? shape.rows : 0;
+    a.nrows = (unsigned)(g.vol / g.L[0]);
+    a.ty = rows_mode ? shape.ty : 1;
+    a.tz = rows_mode ? shape.tz : 1;
+    a.tt = rows_mode ? shape.tt : 1;
+    a.nty = g.L[1] / a.ty;
+    a.ntt = g.L[3] / a.tt;
+    a.inv_per = 1.0f / (float)(a.ty * a.tz * a.tt);
+    a.inv_ty = 1.0f / (float)a.ty;
+    a.inv_tz = 1.0f / (float)a.tz;
+    a.inv_ntt = 1.0f / (float)a.ntt;
+    a.inv_ntyt = 1.0f / (float)a.nty;
+    int threads;
+    long nblocks;
+    if (rows_mode) {
+        threads = shape.rows * (g.L[0] / 2) * g.Ls;
+        nblocks = ((long)a.nrows + shape.rows - 1) / shape.rows;
+    } else {
+        if (shape.spb < 1) shape = default_shape(g);
+        a.spb = shape.spb;
+        threads = shape.spb * g.Ls;
+        nblocks = (g.half + shape.spb - 1) / shape.spb;
+    }
     if (threads > kMaxDhopThreads || threads < 1) return fail(DWF_EINVAL, "hopping kernel: workgroup size out of range");
-    const long nblocks = (g.half + shape.spb - 1) / shape.spb;
     // the specialised kernels use 32-bit byte offsets: every field they touch must be below 4 GiB
     const size_t big = std::max(cb_bytes(g, c.prec_in), cb_bytes(g, c.prec_out));
     const int ls_t = big < (size_t(1) << 32) ? g.Ls : 0;

@@ -57,9 +57,12 @@ inline size_t link_bytes(const Geom &g, int prec) { return (size_t)g.half * 8 * 
 
 // Launch shape of the hopping kernel.
 struct DhopShape {
-    int spb = 0;        // 4D sites per workgroup (workgroup = spb * Ls lanes)
+    int spb = 0;        // site kernel: 4D sites per workgroup (workgroup = spb * Ls lanes)
     int xcd = 1;        // XCD-aware block remap on/off
     int nt_store = 1;   // non-temporal stores of the output (it is not re-read by this launch)
+    int rows = 0;       // > 0: row kernel with this many whole x-rows per workgroup (links and the
+                        //      x-neighbour rows staged in LDS); 0: site kernel
+    int ty = 1, tz = 1, tt = 1;  // row kernel: (y, z, t) tile of the row traversal order
 };
 
 constexpr int kMaxDhopThreads = 512;
@@ -104,6 +107,7 @@ struct dwf_ctx_s {
     double *host_scal = nullptr; // pinned host mirror (16 doubles)
     void *events[2] = {};        // hipEvent_t pair for the solver's lagged stop check
     dwf::DhopShape shape[4][2];  // tuned launch shape per (prec, dagger)
+    size_t lds_limit = 65536;    // LDS bytes one workgroup may allocate on this device
     double inner_tol = 0.0;
     int inner_maxit = 0;
     dwf::CgWork work;
@@ -132,6 +136,9 @@ int launch_convert(const Geom &g, void *out, int out_prec, const void *in, int i
 // Hopping kernel with epilogues (dhop.hip).
 int launch_dhop(dwf_ctx ctx, const DhopCall &c, const DhopShape &shape, hipStream_t st);
 DhopShape default_shape(const Geom &g);
+DhopShape default_row_shape(const Geom &g, int prec, size_t lds_limit);
+size_t row_lds_bytes(int rows, int L0h, int Ls, int prec);
+bool row_shape_ok(const Geom &g, const DhopShape &sh, int prec, size_t lds_limit);
 // M5op family on ncb checkerboard fields (m5.hip).
 int launch_m5(const Geom &g, void *out, const void *in, int dagger, int inverse, long nsites, int prec,
               hipStream_t st);
@@ -141,6 +148,8 @@ void m5inv_coefficients(const Geom &g, double *coef);
 int launch_reduce(double *partials, double *dst, const void *x, const void *y, long n, int prec, int dot,
                   hipStream_t st);
 int launch_axpy(void *y, double ar, double ai, const void *x, long n, int prec, hipStream_t st);
+int launch_fill_pattern(void *f, size_t bytes, int prec, hipStream_t st);
+int launch_count_diff(const void *a, const void *b, size_t bytes, unsigned *count, hipStream_t st);
 
 // Operators composed from kernels (ops.hip).
 int op_mpc(dwf_ctx ctx, void *out, const void *in, int dagger, int prec, hipStream_t st);

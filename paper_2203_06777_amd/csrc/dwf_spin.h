@@ -11,6 +11,9 @@
 
 namespace dwf {
 
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // h = u + TAU * e_MU l for the 3 colours; p holds 24 reals (k = spin*3+colour).
 template <int MU, int TAU, typename A>
 __device__ __forceinline__ void project(const A *__restrict__ p, A *__restrict__ h) {
@@ -51,8 +54,12 @@ __device__ __forceinline__ void mul_reconstruct(const A *__restrict__ w, const A
             for (int b = 0; b < 3; ++b) {
                 const A wr = w[2 * (3 * a + b)], wi = w[2 * (3 * a + b) + 1];
                 const A hr = h[2 * (3 * k + b)], hi = h[2 * (3 * k + b) + 1];
-                re += wr * hr - wi * hi;
-                im += wr * hi + wi * hr;
+                // explicit fused multiply-adds: the library is built with -ffp-contract=off,
+                // so every kernel variant rounds identically and launch shapes agree bitwise
+                re = fma_(wr, hr, re);
+                re = fma_(-wi, hi, re);
+                im = fma_(wr, hi, im);
+                im = fma_(wi, hr, im);
             }
             chi[2 * (3 * k + a)] = re;
             chi[2 * (3 * k + a) + 1] = im;
