@@ -212,7 +212,8 @@ def main():
         from oracle import coracle as C
 
         nthreads = C.num_threads()
-        probe = 512
+        probe = 4096
+        C.dhop_cb(u, psi, 1, 0, rows=(0, probe))  # warm-up (threads, first-touch pages)
         t = time.time()
         C.dhop_cb(u, psi, 1, 0, rows=(0, probe))
         dt = max(time.time() - t, 1e-3)
