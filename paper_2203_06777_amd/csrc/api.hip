@@ -141,6 +141,7 @@ int dwf_create(const dwf_geom *geom, dwf_ctx *out) {
         if (hipMalloc(&c->tmp[k], cb_bytes(c->g, DWF_F64)) != hipSuccess)
             return cleanup(DWF_ENOMEM, "dwf_create: hipMalloc of temporaries failed");
     if (hipMalloc(&c->partials, sizeof(double) * 2 * kRedBlocks) != hipSuccess ||
+        hipMalloc(&c->dhop_partials, sizeof(double) * (size_t)c->g.half) != hipSuccess ||
         hipMalloc(&c->scal, sizeof(double) * 16) != hipSuccess)
         return cleanup(DWF_ENOMEM, "dwf_create: hipMalloc of reduction buffers failed");
     if (hipHostMalloc((void **)&c->host_scal, sizeof(double) * 16, hipHostMallocDefault) != hipSuccess)
@@ -162,6 +163,7 @@ int dwf_destroy(dwf_ctx c) {
         for (void *p : pp) hipFree(p);
     for (void *p : c->tmp) hipFree(p);
     hipFree(c->partials);
+    hipFree(c->dhop_partials);
     hipFree(c->scal);
     if (c->host_scal) hipHostFree(c->host_scal);
     for (void *e : c->events)

@@ -32,8 +32,28 @@ struct DhopArgs {
     unsigned nrows, ty, tz, tt, nty, ntt;
     float inv_per, inv_ty, inv_tz, inv_ntt, inv_ntyt;
     double alpha, beta, d5, mf;
+    double *norm_out;
     double coef[kMaxLs];
 };
+
+// partials[blockIdx.x] = sum over the workgroup's active lanes of |v|^2, by a
+// fixed LDS tree (bitwise reproducible).  Every lane of the workgroup calls it.
+template <typename A>
+__device__ __forceinline__ void block_norm_partial(double *partials, const A *v, bool active) {
+    __shared__ double red[kMaxDhopThreads];
+    double x = 0;
+    if (active)
+#pragma unroll
+        for (int k = 0; k < 24; ++k) x += (double)v[k] * (double)v[k];
+    const int t = threadIdx.x, n = blockDim.x;
+    red[t] = x;
+    __syncthreads();
+    for (int stride = kMaxDhopThreads / 2; stride > 0; stride >>= 1) {
+        if (t < stride && t + stride < n) red[t] += red[t + stride];
+        __syncthreads();
+    }
+    if (t == 0) partials[blockIdx.x] = red[0];
+}
 
 // Apply M5op^-1 (DAG: M5op^-dag) to the Ls-vector v held by the site's lanes,
 // through LDS.  Lower spins (2,3) couple s to s+n, upper spins (0,1) to s-n
@@ -101,8 +121,8 @@ __global__ void __launch_bounds__(kMaxDhopThreads) k_dhop(const DhopArgs a) {
 #pragma unroll
         for (int k = 0; k < 24; ++k) acc[k] = beta * zv[k] + alpha * acc[k];
     } else if constexpr (EPI == EPI_M5) {
-        if (!active) return;
         // out = (5-M5) z(s) - P_- z~(s+1) - P_+ z~(s-1) + alpha D psi   (adjoint: P_+ <-> P_-)
+        if (active) {
         A z0[24], zu[24], zd[24];
         const Off row = zoff - (Off)(s * 16);
         load_spinor_off<PI>(a.z, zoff, Ls * 16, z0);
@@ -115,6 +135,9 @@ __global__ void __launch_bounds__(kMaxDhopThreads) k_dhop(const DhopArgs a) {
         for (int k = 0; k < 12; ++k) acc[k] = d5 * z0[k] - (DAG ? fu * zu[k] : fd * zd[k]) + alpha * acc[k];
 #pragma unroll
         for (int k = 12; k < 24; ++k) acc[k] = d5 * z0[k] - (DAG ? fd * zd[k] : fu * zu[k]) + alpha * acc[k];
+        }
+        if (a.norm_out != nullptr) block_norm_partial(a.norm_out, acc, active);
+        if (!active) return;
     } else {  // EPI_M5INV
         extern __shared__ unsigned char smem[];
         A *lds = reinterpret_cast<A *>(smem);
@@ -164,7 +187,6 @@ __global__ void __launch_bounds__(kMaxDhopThreads) k_dhop_rows(const DhopArgs a)
     using A = typename PT<PI>::A;
     using Off = typename std::conditional<(LS > 0), unsigned, long>::type;
     constexpr int G = PT<PI>::G, NG = 12 / G, R2 = 2 * G;
-    constexpr int LREC = sizeof(A) == 8 ? 18 : 20;  // 16-byte aligned link records in LDS
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int Ls = LS > 0 ? LS : a.Ls;
     const int L0h = (int)a.lat.L0h;
@@ -178,35 +200,20 @@ __global__ void __launch_bounds__(kMaxDhopThreads) k_dhop_rows(const DhopArgs a)
     const long lb = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (long)blockIdx.x;
     const unsigned q0 = (unsigned)lb * (unsigned)a.rows;
 
-    A *lds_link = reinterpret_cast<A *>(smem);
-    const int link_reals = L0h * 8 * LREC;  // per row
-    u32x4 *lds_x = reinterpret_cast<u32x4 *>(smem + (size_t)a.rows * link_reals * sizeof(A));
-    const int VX = L0h * NG * Ls;                       // 16-byte vectors per field row
-    const int VL = L0h * 8 * 18 * PT<PI>::RB / 16;      // 16-byte vectors of links per row
-    for (int v = t; v < a.rows * VL; v += nthr) {
-        const int rr = v / VL, within = v - rr * VL;
-        if (q0 + rr >= a.nrows) continue;
-        unsigned y1, y2, y3;
+    // LDS: the rows' link blocks (as stored in global memory), then the input rows
+    const int VX = L0h * NG * Ls;                   // 16-byte vectors per field row
+    const int VL = L0h * 8 * 18 * PT<PI>::RB / 16;  // 16-byte vectors of links per row
+    u32x4 *lds_l = reinterpret_cast<u32x4 *>(smem);
+    u32x4 *lds_x = lds_l + a.rows * VL;
+    for (int rr = 0; rr < a.rows; ++rr) {
+        if (q0 + rr >= a.nrows) break;
+        unsigned y1, y2, y3;  // uniform across the workgroup
         rowmap(a, q0 + rr, y1, y2, y3);
-        const long prow = y1 + (long)a.lat.L1 * (y2 + (long)a.lat.L2 * y3);
-        const u32x4 raw = *(const u32x4 *)(a.links + (prow * VL + within) * 16);
-        A vals[R2];
-        unpack16<PI>(raw, vals);
-#pragma unroll
-        for (int e = 0; e < R2; ++e) {
-            const int idx = within * R2 + e;  // real index inside the row's link block
-            const int site = idx / 144, rem = idx - site * 144;
-            const int dir = rem / 18, k = rem - dir * 18;
-            lds_link[(rr * L0h + site) * 8 * LREC + dir * LREC + k] = vals[e];
-        }
-    }
-    for (int v = t; v < a.rows * VX; v += nthr) {
-        const int rr = v / VX, within = v - rr * VX;
-        if (q0 + rr >= a.nrows) continue;
-        unsigned y1, y2, y3;
-        rowmap(a, q0 + rr, y1, y2, y3);
-        const long prow = y1 + (long)a.lat.L1 * (y2 + (long)a.lat.L2 * y3);
-        lds_x[v] = *(const u32x4 *)(a.in + (prow * VX + within) * 16);
+        const unsigned prow = y1 + a.lat.L1 * (y2 + a.lat.L2 * y3);
+        const u32x4 *gl = (const u32x4 *)a.links + (size_t)prow * VL;
+        const u32x4 *gx = (const u32x4 *)a.in + (size_t)prow * VX;
+        for (int v = t; v < VL; v += nthr) lds_l[rr * VL + v] = gl[v];
+        for (int v = t; v < VX; v += nthr) lds_x[rr * VX + v] = gx[v];
     }
     __syncthreads();
 
@@ -230,13 +237,13 @@ __global__ void __launch_bounds__(kMaxDhopThreads) k_dhop_rows(const DhopArgs a)
         const long nb6 = (rest + (x2 == 0 ? (long)(L2 - 1) * s2 : -s2)) * L0h + xh;
         const long nb3 = (rest + (x3 + 1 == L3 ? -(long)(L3 - 1) * s3 : s3)) * L0h + xh;
         const long nb7 = (rest + (x3 == 0 ? (long)(L3 - 1) * s3 : -s3)) * L0h + xh;
-        const A *lk = lds_link + (r * L0h + xh) * 8 * LREC;
+        const char *lk = reinterpret_cast<const char *>(lds_l) + (size_t)(r * L0h + xh) * 8 * 18 * PT<PI>::RB;
         const u32x4 *xr = lds_x + r * VX;
         constexpr int SG = DAG ? 1 : -1;
 #define DWF_HOP_LDS(DIR, MU, TAU, LX)                                                        \
     {                                                                                        \
         A w[18], p[24], h[12];                                                               \
-        _Pragma("unroll") for (int k = 0; k < 18; ++k) w[k] = lk[DIR * LREC + k];            \
+        load_link<PI>(lk, 0, DIR, w);                                                        \
         _Pragma("unroll") for (int g = 0; g < NG; ++g) unpack16<PI>(xr[((LX)*NG + g) * Ls + s], p + R2 * g); \
         project<MU, TAU>(p, h);                                                              \
         mul_reconstruct<MU, TAU>(w, h, acc);                                                 \
@@ -244,7 +251,7 @@ __global__ void __launch_bounds__(kMaxDhopThreads) k_dhop_rows(const DhopArgs a)
 #define DWF_HOP_GLB(DIR, MU, TAU, NB)                                                        \
     {                                                                                        \
         A w[18], p[24], h[12];                                                               \
-        _Pragma("unroll") for (int k = 0; k < 18; ++k) w[k] = lk[DIR * LREC + k];            \
+        load_link<PI>(lk, 0, DIR, w);                                                        \
         load_spinor_off<PI>(a.in, spinor_off<PI, Off>(NB, Ls, s), Ls * 16, p);               \
         project<MU, TAU>(p, h);                                                              \
         mul_reconstruct<MU, TAU>(w, h, acc);                                                 \
@@ -275,7 +282,7 @@ __global__ void __launch_bounds__(kMaxDhopThreads) k_dhop_rows(const DhopArgs a)
 #pragma unroll
         for (int k = 0; k < 24; ++k) acc[k] = beta * zv[k] + alpha * acc[k];
     } else if constexpr (EPI == EPI_M5) {
-        if (!active) return;
+        if (active) {
         A z0[24], zu[24], zd[24];
         const Off row = zoff - (Off)(s * 16);
         load_spinor_off<PI>(a.z, zoff, Ls * 16, z0);
@@ -288,6 +295,9 @@ __global__ void __launch_bounds__(kMaxDhopThreads) k_dhop_rows(const DhopArgs a)
         for (int k = 0; k < 12; ++k) acc[k] = d5 * z0[k] - (DAG ? fu * zu[k] : fd * zd[k]) + alpha * acc[k];
 #pragma unroll
         for (int k = 12; k < 24; ++k) acc[k] = d5 * z0[k] - (DAG ? fd * zd[k] : fu * zu[k]) + alpha * acc[k];
+        }
+        if (a.norm_out != nullptr) block_norm_partial(a.norm_out, acc, active);
+        if (!active) return;
     } else {  // EPI_M5INV: the LDS staging area is reused once every lane is done with it
         A *lds = reinterpret_cast<A *>(smem);
 #pragma unroll
@@ -307,9 +317,7 @@ __global__ void __launch_bounds__(kMaxDhopThreads) k_dhop_rows(const DhopArgs a)
 }
 
 size_t row_lds_bytes(int rows, int L0h, int Ls, int prec) {
-    const size_t areal = prec == DWF_F64 ? 8 : 4;
-    const size_t lrec = prec == DWF_F64 ? 18 : 20;
-    return (size_t)rows * ((size_t)L0h * 8 * lrec * areal + (size_t)L0h * Ls * 24 * real_bytes(prec));
+    return (size_t)rows * (size_t)L0h * (8 * 18 + (size_t)Ls * 24) * real_bytes(prec);
 }
 
 bool row_shape_ok(const Geom &g, const DhopShape &sh, int prec, size_t lds_limit) {
@@ -422,6 +430,7 @@ int launch_dhop(dwf_ctx ctx, const DhopCall &c, const DhopShape &shape_in, hipSt
     a.nt_store = shape.nt_store;
     a.alpha = c.alpha;
     a.beta = c.beta;
+    a.norm_out = c.epi == EPI_M5 ? c.norm_out : nullptr;
     a.d5 = 5.0 - g.M5;
     a.mf = g.mf;
     m5inv_coefficients(g, a.coef);
@@ -450,6 +459,7 @@ int launch_dhop(dwf_ctx ctx, const DhopCall &c, const DhopShape &shape_in, hipSt
         nblocks = (g.half + shape.spb - 1) / shape.spb;
     }
     if (threads > kMaxDhopThreads || threads < 1) return fail(DWF_EINVAL, "hopping kernel: workgroup size out of range");
+    if (c.nparts_out) *c.nparts_out = nblocks;
     // the specialised kernels use 32-bit byte offsets: every field they touch must be below 4 GiB
     const size_t big = std::max(cb_bytes(g, c.prec_in), cb_bytes(g, c.prec_out));
     const int ls_t = big < (size_t(1) << 32) ? g.Ls : 0;

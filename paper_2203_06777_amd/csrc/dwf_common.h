@@ -84,6 +84,8 @@ struct DhopCall {
     int epi;
     double alpha, beta;
     int prec_in, prec_out;  // links use prec_in
+    double *norm_out = nullptr;  // EPI_M5 only: per-workgroup partial sums of |out|^2 (FP64, fixed order)
+    long *nparts_out = nullptr;  // receives the number of partials written
 };
 
 // Solver workspace (allocated on first solve).
@@ -103,6 +105,7 @@ struct dwf_ctx_s {
     bool gauge_set = false;
     void *tmp[2] = {};       // FP64-sized checkerboard temporaries for M_pc
     double *partials = nullptr;  // reduction partials (2 * kRedBlocks doubles)
+    double *dhop_partials = nullptr;  // one FP64 partial per hopping-kernel workgroup (V/2 doubles)
     double *scal = nullptr;      // device scalars of the solvers
     double *host_scal = nullptr; // pinned host mirror (16 doubles)
     void *events[2] = {};        // hipEvent_t pair for the solver's lagged stop check
@@ -153,8 +156,10 @@ int launch_count_diff(const void *a, const void *b, size_t bytes, unsigned *coun
 
 // Operators composed from kernels (ops.hip).
 int op_mpc(dwf_ctx ctx, void *out, const void *in, int dagger, int prec, hipStream_t st);
-int op_mdagm(dwf_ctx ctx, void *out, const void *in, int prec, void *tmp_o, hipStream_t st);
-int op_mdagm_mixed(dwf_ctx ctx, void *out, int prec_out, const void *in, int prec, hipStream_t st);
+int op_mdagm(dwf_ctx ctx, void *out, const void *in, int prec, void *tmp_o, hipStream_t st, double *mp_norm = nullptr,
+             long *nparts = nullptr);
+int op_mdagm_mixed(dwf_ctx ctx, void *out, int prec_out, const void *in, int prec, hipStream_t st,
+                   double *mp_norm = nullptr, long *nparts = nullptr);
 
 // Solvers (solver.hip).
 int cg_solve(dwf_ctx ctx, void *x, const void *b, double tol, int maxit, int mode, dwf_cg_stats *stats,

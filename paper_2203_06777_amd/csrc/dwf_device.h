@@ -13,10 +13,10 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 // ---- bf16 <-> f32 (round to nearest even; NaN stays NaN) -------------------
 __device__ __host__ inline unsigned short f32_to_bf16_bits(float f) {
-    unsigned int u = __builtin_bit_cast(unsigned int, f);
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (unsigned short)((u >> 16) | 0x40);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
+    const unsigned int u = __builtin_bit_cast(unsigned int, f);
+    const unsigned int rounded = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+    const unsigned int quiet = (u >> 16) | 0x40u;  // NaN stays NaN (quiet bit set)
+    return (unsigned short)((u & 0x7fffffffu) > 0x7f800000u ? quiet : rounded);
 }
 __device__ __host__ inline float bf16_bits_to_f32(unsigned short b) {
     return __builtin_bit_cast(float, (unsigned int)b << 16);

@@ -29,15 +29,16 @@ __device__ inline void block_sum1(double &a) {
     }
 }
 
-__device__ inline double sum_partials(const double *partials) {
+__device__ inline double sum_partials(const double *partials, long n = kRedBlocks, int stride = 2) {
     double v = 0;
-    for (int k = threadIdx.x; k < kRedBlocks; k += kRedThreads) v += partials[2 * k];
+    for (long k = threadIdx.x; k < n; k += kRedThreads) v += partials[stride * k];
     block_sum1(v);
     return v;
 }
 
-__global__ void __launch_bounds__(kRedThreads) k_cg_alpha(double *scal, const double *partials) {
-    const double pap = sum_partials(partials);
+// alpha = |r|^2 / <p, A p>, with <p, A p> = |M_pc p|^2 summed from the hopping kernel's partials.
+__global__ void __launch_bounds__(kRedThreads) k_cg_alpha(double *scal, const double *partials, long nparts) {
+    const double pap = sum_partials(partials, nparts, 1);
     if (threadIdx.x != 0 || scal[S_DONE] != 0) return;
     scal[S_PAP] = pap;
     if (!isfinite(pap) || pap <= 0.0) {
@@ -207,14 +208,13 @@ static int cg_core(dwf_ctx ctx, int vprec, int oprec, void *x, void *r, void *p,
     double *hs = ctx->host_scal;
     int it = 0, status = 0;
     for (; it < budget; ++it) {
-        // Ap
-        if (vprec == DWF_F64) rc = op_mdagm(ctx, ap, p, DWF_F64, ctx->tmp[1], st);
-        else if (sixteen) rc = op_mdagm_mixed(ctx, ap, DWF_F32, p16, oprec, st);
-        else rc = op_mdagm(ctx, ap, p, DWF_F32, ctx->tmp[1], st);
+        // Ap, and <p, A p> = |M_pc p|^2 from the M_pc kernel's workgroup partials -> alpha
+        long nparts = 0;
+        if (vprec == DWF_F64) rc = op_mdagm(ctx, ap, p, DWF_F64, ctx->tmp[1], st, ctx->dhop_partials, &nparts);
+        else if (sixteen) rc = op_mdagm_mixed(ctx, ap, DWF_F32, p16, oprec, st, ctx->dhop_partials, &nparts);
+        else rc = op_mdagm(ctx, ap, p, DWF_F32, ctx->tmp[1], st, ctx->dhop_partials, &nparts);
         if (rc) return rc;
-        // <p, Ap> -> alpha
-        if ((rc = launch_reduce(ctx->partials, nullptr, p, ap, n, vprec, 1, st))) return rc;
-        hipLaunchKernelGGL(k_cg_alpha, 1, kRedThreads, 0, st, ctx->scal, ctx->partials);
+        hipLaunchKernelGGL(k_cg_alpha, 1, kRedThreads, 0, st, ctx->scal, ctx->dhop_partials, nparts);
         // x, r update and |r|^2 -> beta, stop flag
         if (vprec == DWF_F64)
             hipLaunchKernelGGL(k_cg_xr<DWF_F64>, kRedBlocks, kRedThreads, 0, st, (u32x4 *)x, (u32x4 *)r,
