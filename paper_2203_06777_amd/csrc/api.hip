@@ -158,18 +158,18 @@ int dwf_create(const dwf_geom *geom, dwf_ctx *out) {
 
 int dwf_destroy(dwf_ctx c) {
     if (!c) return DWF_OK;
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();
     for (auto &pp : c->links)
-        for (void *p : pp) hipFree(p);
-    for (void *p : c->tmp) hipFree(p);
-    hipFree(c->partials);
-    hipFree(c->dhop_partials);
-    hipFree(c->scal);
-    if (c->host_scal) hipHostFree(c->host_scal);
+        for (void *p : pp) (void)hipFree(p);
+    for (void *p : c->tmp) (void)hipFree(p);
+    (void)hipFree(c->partials);
+    (void)hipFree(c->dhop_partials);
+    (void)hipFree(c->scal);
+    if (c->host_scal) (void)hipHostFree(c->host_scal);
     for (void *e : c->events)
-        if (e) hipEventDestroy((hipEvent_t)e);
+        if (e) (void)hipEventDestroy((hipEvent_t)e);
     CgWork &w = c->work;
-    for (void *p : {w.x64, w.r64, w.p64, w.ap64, w.e32, w.r32, w.p32, w.ap32, w.p16, w.full_tmp}) hipFree(p);
+    for (void *p : {w.x64, w.r64, w.p64, w.ap64, w.e32, w.r32, w.p32, w.p16, w.full_tmp}) (void)hipFree(p);
     delete c;
     return DWF_OK;
 }
@@ -415,10 +415,10 @@ int dwf_tune(dwf_ctx ctx, int prec, int dagger, double *best_us, void *stream) {
     void *in = nullptr, *out = nullptr, *ref = nullptr;
     unsigned *ndiff = nullptr;
     auto release = [&]() {
-        hipFree(in);
-        hipFree(out);
-        hipFree(ref);
-        hipFree(ndiff);
+        (void)hipFree(in);
+        (void)hipFree(out);
+        (void)hipFree(ref);
+        (void)hipFree(ndiff);
     };
     if (hipMalloc(&in, cb) != hipSuccess || hipMalloc(&out, cb) != hipSuccess || hipMalloc(&ref, cb) != hipSuccess ||
         hipMalloc((void **)&ndiff, sizeof(unsigned)) != hipSuccess) {
@@ -509,8 +509,8 @@ int dwf_tune(dwf_ctx ctx, int prec, int dagger, double *best_us, void *stream) {
             best_s = s;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     hipStreamSynchronize(st);
     release();
     if (status != DWF_OK) return status;

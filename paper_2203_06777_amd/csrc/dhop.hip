@@ -33,6 +33,7 @@ struct DhopArgs {
     float inv_per, inv_ty, inv_tz, inv_ntt, inv_ntyt;
     double alpha, beta, d5, mf;
     double *norm_out;
+    const double *cg_alpha, *cg_live;
     double coef[kMaxLs];
 };
 
@@ -88,6 +89,44 @@ __device__ __forceinline__ void m5inv_lds(const DhopArgs &a, int Ls, A *lds, int
     for (int k = 0; k < 24; ++k) v[k] = o[k];
 }
 
+// acc = M5op z + alpha acc at lane (c, s) (adjoint: P_+ <-> P_-), zoff = offset of z(c, s):
+// M5op z(s) = (5-M5) z(s) - P_- z~(s+1) - P_+ z~(s-1), z~ carrying -mf across the wall.
+template <int PI, int DAG, typename Off>
+__device__ __forceinline__ void m5_combine(const DhopArgs &a, Off zoff, int Ls, int s, typename PT<PI>::A *acc) {
+    using A = typename PT<PI>::A;
+    A z0[24], zu[24], zd[24];
+    const Off row = zoff - (Off)(s * 16);
+    load_spinor_off<PI>(a.z, zoff, Ls * 16, z0);
+    load_spinor_off<PI>(a.z, row + (Off)((s + 1 < Ls ? s + 1 : 0) * 16), Ls * 16, zu);
+    load_spinor_off<PI>(a.z, row + (Off)((s >= 1 ? s - 1 : Ls - 1) * 16), Ls * 16, zd);
+    const A fu = s + 1 < Ls ? (A)1 : (A)(-a.mf);
+    const A fd = s >= 1 ? (A)1 : (A)(-a.mf);
+    const A d5 = (A)a.d5, alpha = (A)a.alpha;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = d5 * z0[k] - (DAG ? fu * zu[k] : fd * zd[k]) + alpha * acc[k];
+#pragma unroll
+    for (int k = 12; k < 24; ++k) acc[k] = d5 * z0[k] - (DAG ? fd * zd[k] : fu * zu[k]) + alpha * acc[k];
+}
+
+// CG residual update with the lane's y = A p in registers: r(c, s) -= cg_alpha * y in
+// r's own precision PO (FP32 or FP64), then the workgroup's partial of the new |r|^2.
+// Every lane of the workgroup calls it.
+template <int PI, int PO, typename Off>
+__device__ __forceinline__ void cg_update(const DhopArgs &a, long c, int Ls, int s, bool active,
+                                          const typename PT<PI>::A *y) {
+    using RA = typename PT<PO>::A;
+    RA rv[24];
+    const Off roff = spinor_off<PO, Off>(c, Ls, s);
+    if (active) {
+        const RA ca = (RA)*a.cg_alpha;
+        load_spinor_off<PO>(a.out, roff, Ls * 16, rv);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) rv[k] = rv[k] - ca * (RA)y[k];
+    }
+    block_norm_partial(a.norm_out, rv, active);
+    if (active) store_spinor_off<PO>(a.out, roff, Ls * 16, rv, false);
+}
+
 // LS > 0: Ls fixed at compile time and 32-bit field offsets; LS == 0: generic.
 template <int PI, int PO, int DAG, int EPI, int LS>
 __global__ void __launch_bounds__(kMaxDhopThreads) k_dhop(const DhopArgs a) {
@@ -100,6 +139,8 @@ __global__ void __launch_bounds__(kMaxDhopThreads) k_dhop(const DhopArgs a) {
     const long blk = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (long)blockIdx.x;
     const long c = blk * a.spb + j;
     const bool active = c < a.half;
+    if constexpr (EPI == EPI_CG)
+        if (*a.cg_live == 0) return;  // the solver has stopped: r stays as it is
 
     A acc[24];
 #pragma unroll
@@ -121,23 +162,13 @@ __global__ void __launch_bounds__(kMaxDhopThreads) k_dhop(const DhopArgs a) {
 #pragma unroll
         for (int k = 0; k < 24; ++k) acc[k] = beta * zv[k] + alpha * acc[k];
     } else if constexpr (EPI == EPI_M5) {
-        // out = (5-M5) z(s) - P_- z~(s+1) - P_+ z~(s-1) + alpha D psi   (adjoint: P_+ <-> P_-)
-        if (active) {
-        A z0[24], zu[24], zd[24];
-        const Off row = zoff - (Off)(s * 16);
-        load_spinor_off<PI>(a.z, zoff, Ls * 16, z0);
-        load_spinor_off<PI>(a.z, row + (Off)((s + 1 < Ls ? s + 1 : 0) * 16), Ls * 16, zu);
-        load_spinor_off<PI>(a.z, row + (Off)((s >= 1 ? s - 1 : Ls - 1) * 16), Ls * 16, zd);
-        const A fu = s + 1 < Ls ? (A)1 : (A)(-a.mf);
-        const A fd = s >= 1 ? (A)1 : (A)(-a.mf);
-        const A d5 = (A)a.d5;
-#pragma unroll
-        for (int k = 0; k < 12; ++k) acc[k] = d5 * z0[k] - (DAG ? fu * zu[k] : fd * zd[k]) + alpha * acc[k];
-#pragma unroll
-        for (int k = 12; k < 24; ++k) acc[k] = d5 * z0[k] - (DAG ? fd * zd[k] : fu * zu[k]) + alpha * acc[k];
-        }
+        if (active) m5_combine<PI, DAG>(a, zoff, Ls, s, acc);
         if (a.norm_out != nullptr) block_norm_partial(a.norm_out, acc, active);
         if (!active) return;
+    } else if constexpr (EPI == EPI_CG) {
+        if (active) m5_combine<PI, DAG>(a, zoff, Ls, s, acc);
+        cg_update<PI, PO, Off>(a, c, Ls, s, active, acc);
+        return;
     } else {  // EPI_M5INV
         extern __shared__ unsigned char smem[];
         A *lds = reinterpret_cast<A *>(smem);
@@ -199,6 +230,8 @@ __global__ void __launch_bounds__(kMaxDhopThreads) k_dhop_rows(const DhopArgs a)
     const int s = wi - xh * Ls;
     const long lb = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (long)blockIdx.x;
     const unsigned q0 = (unsigned)lb * (unsigned)a.rows;
+    if constexpr (EPI == EPI_CG)
+        if (*a.cg_live == 0) return;  // the solver has stopped: r stays as it is
 
     // LDS: the rows' link blocks (as stored in global memory), then the input rows
     const int VX = L0h * NG * Ls;                   // 16-byte vectors per field row
@@ -282,22 +315,13 @@ __global__ void __launch_bounds__(kMaxDhopThreads) k_dhop_rows(const DhopArgs a)
 #pragma unroll
         for (int k = 0; k < 24; ++k) acc[k] = beta * zv[k] + alpha * acc[k];
     } else if constexpr (EPI == EPI_M5) {
-        if (active) {
-        A z0[24], zu[24], zd[24];
-        const Off row = zoff - (Off)(s * 16);
-        load_spinor_off<PI>(a.z, zoff, Ls * 16, z0);
-        load_spinor_off<PI>(a.z, row + (Off)((s + 1 < Ls ? s + 1 : 0) * 16), Ls * 16, zu);
-        load_spinor_off<PI>(a.z, row + (Off)((s >= 1 ? s - 1 : Ls - 1) * 16), Ls * 16, zd);
-        const A fu = s + 1 < Ls ? (A)1 : (A)(-a.mf);
-        const A fd = s >= 1 ? (A)1 : (A)(-a.mf);
-        const A d5 = (A)a.d5;
-#pragma unroll
-        for (int k = 0; k < 12; ++k) acc[k] = d5 * z0[k] - (DAG ? fu * zu[k] : fd * zd[k]) + alpha * acc[k];
-#pragma unroll
-        for (int k = 12; k < 24; ++k) acc[k] = d5 * z0[k] - (DAG ? fd * zd[k] : fu * zu[k]) + alpha * acc[k];
-        }
+        if (active) m5_combine<PI, DAG>(a, zoff, Ls, s, acc);
         if (a.norm_out != nullptr) block_norm_partial(a.norm_out, acc, active);
         if (!active) return;
+    } else if constexpr (EPI == EPI_CG) {
+        if (active) m5_combine<PI, DAG>(a, zoff, Ls, s, acc);
+        cg_update<PI, PO, Off>(a, c, Ls, s, active, acc);
+        return;
     } else {  // EPI_M5INV: the LDS staging area is reused once every lane is done with it
         A *lds = reinterpret_cast<A *>(smem);
 #pragma unroll
@@ -397,6 +421,12 @@ static int launch_t(const DhopArgs &a, int ls_t, long nblocks, int threads, hipS
 
 template <int PI, int PO>
 static int launch_pp(const DhopArgs &a, int ls_t, int dagger, int epi, long nb, int th, hipStream_t st) {
+    if (epi == EPI_CG) {
+        // the solver's residual update: adjoint kernel, r in FP32 or FP64
+        if constexpr (PO == DWF_F32 || PO == DWF_F64)
+            if (dagger) return launch_t<PI, PO, 1, EPI_CG>(a, ls_t, nb, th, st);
+        return fail(DWF_EUNSUP, "hopping kernel: CG epilogue needs the adjoint and an FP32/FP64 residual");
+    }
     if (dagger) {
         switch (epi) {
             case EPI_SCALE: return launch_t<PI, PO, 1, EPI_SCALE>(a, ls_t, nb, th, st);
@@ -430,7 +460,11 @@ int launch_dhop(dwf_ctx ctx, const DhopCall &c, const DhopShape &shape_in, hipSt
     a.nt_store = shape.nt_store;
     a.alpha = c.alpha;
     a.beta = c.beta;
-    a.norm_out = c.epi == EPI_M5 ? c.norm_out : nullptr;
+    a.norm_out = (c.epi == EPI_M5 || c.epi == EPI_CG) ? c.norm_out : nullptr;
+    a.cg_alpha = c.cg_alpha;
+    a.cg_live = c.cg_live;
+    if (c.epi == EPI_CG && (!c.norm_out || !c.cg_alpha || !c.cg_live || !c.z))
+        return fail(DWF_EINVAL, "hopping kernel: CG epilogue needs z, partials and the solver scalars");
     a.d5 = 5.0 - g.M5;
     a.mf = g.mf;
     m5inv_coefficients(g, a.coef);

@@ -73,6 +73,8 @@ enum Epi {
     EPI_AXPY = 1,   // out = beta * z + alpha * D psi
     EPI_M5 = 2,     // out = M5op(z) + alpha * D psi   (M5op^dag when dagger)
     EPI_M5INV = 3,  // out = M5op^-1 (beta * z + alpha * D psi)   (M5op^-dag when dagger; z optional)
+    EPI_CG = 4,     // CG step: y = M5op(z) + alpha * D psi is A p; out (= r, FP32 or FP64, read and
+                    // written) -= (*cg_alpha) * y when *cg_live != 0, with |r|^2 partials in norm_out
 };
 
 struct DhopCall {
@@ -84,15 +86,16 @@ struct DhopCall {
     int epi;
     double alpha, beta;
     int prec_in, prec_out;  // links use prec_in
-    double *norm_out = nullptr;  // EPI_M5 only: per-workgroup partial sums of |out|^2 (FP64, fixed order)
+    double *norm_out = nullptr;  // EPI_M5, EPI_CG: per-workgroup partial sums of |out|^2 (FP64, fixed order)
     long *nparts_out = nullptr;  // receives the number of partials written
+    const double *cg_alpha = nullptr, *cg_live = nullptr;  // EPI_CG: device scalars of the solver
 };
 
 // Solver workspace (allocated on first solve).
 struct CgWork {
     size_t bytes = 0;
     void *x64 = nullptr, *r64 = nullptr, *p64 = nullptr, *ap64 = nullptr;
-    void *e32 = nullptr, *r32 = nullptr, *p32 = nullptr, *ap32 = nullptr, *p16 = nullptr;
+    void *e32 = nullptr, *r32 = nullptr, *p32 = nullptr, *p16 = nullptr;
     void *full_tmp = nullptr;  // one full FP64 field for dwf_solve
 };
 
@@ -155,11 +158,11 @@ int launch_fill_pattern(void *f, size_t bytes, int prec, hipStream_t st);
 int launch_count_diff(const void *a, const void *b, size_t bytes, unsigned *count, hipStream_t st);
 
 // Operators composed from kernels (ops.hip).
-int op_mpc(dwf_ctx ctx, void *out, const void *in, int dagger, int prec, hipStream_t st);
-int op_mdagm(dwf_ctx ctx, void *out, const void *in, int prec, void *tmp_o, hipStream_t st, double *mp_norm = nullptr,
-             long *nparts = nullptr);
-int op_mdagm_mixed(dwf_ctx ctx, void *out, int prec_out, const void *in, int prec, hipStream_t st,
-                   double *mp_norm = nullptr, long *nparts = nullptr);
+int op_mpc(dwf_ctx ctx, void *out, const void *in, int dagger, int prec, hipStream_t st, double *norm_out = nullptr,
+           long *nparts = nullptr);
+int op_mdagm(dwf_ctx ctx, void *out, const void *in, int prec, void *tmp_o, hipStream_t st);
+int op_mpcdag_cg(dwf_ctx ctx, void *r, int prec_r, const void *y, int prec, const double *cg_alpha,
+                 const double *cg_live, double *partials, long *nparts, hipStream_t st);
 
 // Solvers (solver.hip).
 int cg_solve(dwf_ctx ctx, void *x, const void *b, double tol, int maxit, int mode, dwf_cg_stats *stats,

@@ -18,26 +18,30 @@ static int two_step(dwf_ctx ctx, void *out, int prec_out, const void *in, void *
     return launch_dhop(ctx, c2, sh, st);
 }
 
-int op_mpc(dwf_ctx ctx, void *out, const void *in, int dagger, int prec, hipStream_t st) {
-    return two_step(ctx, out, prec, in, ctx->tmp[0], dagger, prec, st);
+// With norm_out set, the workgroups of the second kernel also write partial sums
+// of |M_pc in|^2 (count in *nparts).
+int op_mpc(dwf_ctx ctx, void *out, const void *in, int dagger, int prec, hipStream_t st, double *norm_out,
+           long *nparts) {
+    return two_step(ctx, out, prec, in, ctx->tmp[0], dagger, prec, st, norm_out, nparts);
 }
 
-// With mp_norm set, the workgroups of the M_pc kernel also write partial sums of
-// |M_pc in|^2 = <in, M_pc^dag M_pc in> (count in *nparts) for the solver.
-int op_mdagm(dwf_ctx ctx, void *out, const void *in, int prec, void *tmp_o, hipStream_t st, double *mp_norm,
-             long *nparts) {
-    int rc = two_step(ctx, tmp_o, prec, in, ctx->tmp[0], 0, prec, st, mp_norm, nparts);
+int op_mdagm(dwf_ctx ctx, void *out, const void *in, int prec, void *tmp_o, hipStream_t st) {
+    int rc = two_step(ctx, tmp_o, prec, in, ctx->tmp[0], 0, prec, st);
     if (rc) return rc;
     return two_step(ctx, out, prec, tmp_o, ctx->tmp[0], 1, prec, st);
 }
 
-// M_pc^dag M_pc with 16-bit (or FP32) intermediate fields and the final output
-// written in prec_out (FP32 for the inner solver's A p).
-int op_mdagm_mixed(dwf_ctx ctx, void *out, int prec_out, const void *in, int prec, hipStream_t st, double *mp_norm,
-                   long *nparts) {
-    int rc = two_step(ctx, ctx->tmp[1], prec, in, ctx->tmp[0], 0, prec, st, mp_norm, nparts);
+// One CG step on M_pc^dag M_pc with y = M_pc p already computed: the adjoint
+// Schur complement of y is never stored, the second kernel's epilogue applies
+// r -= alpha M_pc^dag y to r (prec_r) and writes partials of the new |r|^2.
+int op_mpcdag_cg(dwf_ctx ctx, void *r, int prec_r, const void *y, int prec, const double *cg_alpha,
+                 const double *cg_live, double *partials, long *nparts, hipStream_t st) {
+    const DhopShape &sh = ctx->shape[prec][1];
+    DhopCall c1{y, ctx->tmp[0], nullptr, 0, 1, EPI_M5INV, 1.0, 0.0, prec, prec};
+    int rc = launch_dhop(ctx, c1, sh, st);
     if (rc) return rc;
-    return two_step(ctx, out, prec_out, ctx->tmp[1], ctx->tmp[0], 1, prec, st);
+    DhopCall c2{ctx->tmp[0], r, y, 1, 1, EPI_CG, -0.25, 0.0, prec, prec_r, partials, nparts, cg_alpha, cg_live};
+    return launch_dhop(ctx, c2, sh, st);
 }
 
 }  // namespace dwf

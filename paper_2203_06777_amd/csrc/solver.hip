@@ -1,12 +1,20 @@
 // Conjugate gradient on the Schur normal operator M_pc^dag M_pc, in FP64 and
 // as FP64 defect correction around a low-precision inner CG.
 //
-// The CG scalars (alpha, beta, |r|^2, the stop flag) live in device memory and
-// are produced by single-block kernels from the FP64 block partials, so an
-// iteration is a fixed sequence of launches with no host round trip.  The host
-// reads the stop flag one iteration behind (an async copy into pinned memory
-// and an event), so the GPU queue never drains; once the flag is set, the
-// update kernels of any iteration already queued leave x, r and p untouched.
+// An iteration is six launches with no host round trip:
+//   y = M_pc p                     two hopping kernels; the second also writes
+//                                  partials of |y|^2 = <p, A p>
+//   alpha = |r|^2 / |y|^2          one single-block kernel
+//   r -= alpha M_pc^dag y          two hopping kernels; A p lives only in registers of
+//                                  the second, which updates r and writes |r|^2 partials
+//   beta, |r|^2, stop flag         one single-block kernel
+//   x += alpha p ; p = r + beta p  one streaming kernel
+// The scalars live in device memory.  The host reads the stop flag one
+// iteration behind (an async copy into pinned memory and an event), so the GPU
+// queue never drains; an iteration queued after the stop finds the live flag
+// cleared by its alpha kernel and leaves x, r and p untouched.  With a 16-bit
+// operator the search direction is kept only in that format: it is the
+// hopping kernels' input, and x moves along exactly the p that A was applied to.
 #include <chrono>
 #include <cmath>
 
@@ -14,43 +22,56 @@
 
 namespace dwf {
 
-enum { S_RR = 0, S_PAP = 1, S_ALPHA = 2, S_BETA = 3, S_STOP = 4, S_DONE = 5, S_ITERS = 6, S_RED = 8 };
-constexpr int kScal = 16;
+enum { S_RR = 0, S_PAP = 1, S_ALPHA = 2, S_BETA = 3, S_STOP = 4, S_DONE = 5, S_ITERS = 6, S_LIVE = 7, S_RED = 8 };
+constexpr int kSumThreads = 1024;
 
-__device__ inline void block_sum1(double &a) {
-    __shared__ double sa[kRedThreads / 64];
+// Sum of n per-workgroup partials by one workgroup of kSumThreads lanes, in a
+// fixed order: four independent strided loads per round keep the requests in
+// flight (the sums are latency bound), then a wave shuffle tree and an LDS pass.
+// The result is valid in thread 0.
+__device__ inline double sum_partials(const double *partials, long n) {
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    long k = threadIdx.x;
+    for (; k + 3 * kSumThreads < n; k += 4 * kSumThreads) {
+        a0 += partials[k];
+        a1 += partials[k + kSumThreads];
+        a2 += partials[k + 2 * kSumThreads];
+        a3 += partials[k + 3 * kSumThreads];
+    }
+    for (; k < n; k += kSumThreads) a0 += partials[k];
+    double v = (a0 + a1) + (a2 + a3);
+    __shared__ double sa[kSumThreads / 64];
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) a += __shfl_xor(a, off, 64);
-    if (threadIdx.x % 64 == 0) sa[threadIdx.x / 64] = a;
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (threadIdx.x % 64 == 0) sa[threadIdx.x / 64] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
-        a = 0;
-        for (int k = 0; k < kRedThreads / 64; ++k) a += sa[k];
+        v = 0;
+        for (int w = 0; w < kSumThreads / 64; ++w) v += sa[w];
     }
-}
-
-__device__ inline double sum_partials(const double *partials, long n = kRedBlocks, int stride = 2) {
-    double v = 0;
-    for (long k = threadIdx.x; k < n; k += kRedThreads) v += partials[stride * k];
-    block_sum1(v);
     return v;
 }
 
-// alpha = |r|^2 / <p, A p>, with <p, A p> = |M_pc p|^2 summed from the hopping kernel's partials.
-__global__ void __launch_bounds__(kRedThreads) k_cg_alpha(double *scal, const double *partials, long nparts) {
-    const double pap = sum_partials(partials, nparts, 1);
-    if (threadIdx.x != 0 || scal[S_DONE] != 0) return;
+// alpha = |r|^2 / <p, A p>, with <p, A p> = |M_pc p|^2 summed from the hopping kernel's
+// partials; S_LIVE says whether this iteration updates x, r and p.
+__global__ void __launch_bounds__(kSumThreads) k_cg_alpha(double *scal, const double *partials, long nparts) {
+    const double pap = sum_partials(partials, nparts);
+    if (threadIdx.x != 0) return;
+    scal[S_LIVE] = 0;
+    if (scal[S_DONE] != 0) return;
     scal[S_PAP] = pap;
     if (!isfinite(pap) || pap <= 0.0) {
         scal[S_DONE] = 2;
         return;
     }
     scal[S_ALPHA] = scal[S_RR] / pap;
+    scal[S_LIVE] = 1;
 }
 
-__global__ void __launch_bounds__(kRedThreads) k_cg_beta(double *scal, const double *partials) {
-    const double rr = sum_partials(partials);
-    if (threadIdx.x != 0 || scal[S_DONE] != 0) return;
+// |r|^2 of the updated residual -> beta and the stop flag.
+__global__ void __launch_bounds__(kSumThreads) k_cg_beta(double *scal, const double *partials, long nparts) {
+    const double rr = sum_partials(partials, nparts);
+    if (threadIdx.x != 0 || scal[S_LIVE] == 0) return;
     scal[S_ITERS] += 1;
     if (!isfinite(rr)) {
         scal[S_DONE] = 2;
@@ -61,55 +82,29 @@ __global__ void __launch_bounds__(kRedThreads) k_cg_beta(double *scal, const dou
     if (rr <= scal[S_STOP]) scal[S_DONE] = 1;
 }
 
-// x += alpha p ; r -= alpha Ap ; partial |r|^2.
-template <int P>
-__global__ void __launch_bounds__(kRedThreads) k_cg_xr(u32x4 *x, u32x4 *r, const u32x4 *p, const u32x4 *ap,
-                                                       const double *scal, double *partials, long nv) {
-    if (scal[S_DONE] != 0) return;
-    constexpr int R = 2 * PT<P>::G;
-    using A = typename PT<P>::A;
-    const A alpha = (A)scal[S_ALPHA];
-    double acc = 0;
-    for (long v = (long)blockIdx.x * kRedThreads + threadIdx.x; v < nv; v += (long)gridDim.x * kRedThreads) {
-        A xv[R], rv[R], pv[R], av[R];
-        unpack16<P>(x[v], xv);
-        unpack16<P>(r[v], rv);
-        unpack16<P>(p[v], pv);
-        unpack16<P>(ap[v], av);
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            xv[k] += alpha * pv[k];
-            rv[k] -= alpha * av[k];
-            acc += (double)rv[k] * rv[k];
-        }
-        x[v] = pack16<P>(xv);
-        r[v] = pack16<P>(rv);
-    }
-    block_sum1(acc);
-    if (threadIdx.x == 0) {
-        partials[2 * blockIdx.x] = acc;
-        partials[2 * blockIdx.x + 1] = 0;
-    }
-}
-
-// p = r + beta p, optionally also storing p in the 16-bit operator precision.
-template <int P, int P16>
-__global__ void __launch_bounds__(256) k_cg_p(u32x4 *p, const u32x4 *r, u32x4 *p16, const double *scal, long nrows,
-                                              int Ls) {
-    if (scal[S_DONE] != 0) return;
+// x += alpha p ; p = r + beta p.  x and r in PV (FP64 or FP32), p in PP (PV, or the
+// 16-bit operator format), arithmetic in PV's type.
+template <int PV, int PP>
+__global__ void __launch_bounds__(256) k_cg_px(u32x4 *x, const u32x4 *r, u32x4 *p, const double *scal, long nrows,
+                                               int Ls) {
+    if (scal[S_LIVE] == 0) return;
     const long t = (long)blockIdx.x * 256 + threadIdx.x;
     if (t >= nrows * Ls) return;
     const long c = t / Ls;
     const int s = (int)(t - c * Ls);
-    using A = typename PT<P>::A;
-    const A beta = (A)scal[S_BETA];
-    A pv[24], rv[24];
-    load_spinor<P>(p, c, Ls, s, pv);
-    load_spinor<P>(r, c, Ls, s, rv);
+    using A = typename PT<PV>::A;
+    const A alpha = (A)scal[S_ALPHA], beta = (A)scal[S_BETA];
+    A xv[24], rv[24], pv[24];
+    load_spinor<PP>(p, c, Ls, s, pv);
+    load_spinor<PV>(x, c, Ls, s, xv);
+    load_spinor<PV>(r, c, Ls, s, rv);
 #pragma unroll
-    for (int k = 0; k < 24; ++k) pv[k] = rv[k] + beta * pv[k];
-    store_spinor<P>(p, c, Ls, s, pv);
-    if (P16 >= 0) store_spinor<(P16 < 0 ? P : P16)>(p16, c, Ls, s, pv);
+    for (int k = 0; k < 24; ++k) {
+        xv[k] = xv[k] + alpha * pv[k];
+        pv[k] = rv[k] + beta * pv[k];
+    }
+    store_spinor<PV>(x, c, Ls, s, xv);
+    store_spinor<PP>(p, c, Ls, s, pv);
 }
 
 // out = factor * in with a precision change.
@@ -147,6 +142,7 @@ __global__ void k_set_scalars(double *scal, double stop) {
     scal[S_STOP] = stop;
     scal[S_DONE] = 0;
     scal[S_ITERS] = 0;
+    scal[S_LIVE] = 0;
 }
 
 static inline unsigned nb256(long n) { return (unsigned)((n + 255) / 256); }
@@ -157,14 +153,14 @@ static int ensure_work(dwf_ctx ctx) {
     const Geom &g = ctx->g;
     const size_t b64 = cb_bytes(g, DWF_F64), b32 = cb_bytes(g, DWF_F32), b16 = cb_bytes(g, DWF_F16);
     void **f64[] = {&w.x64, &w.r64, &w.p64, &w.ap64};
-    void **f32[] = {&w.e32, &w.r32, &w.p32, &w.ap32};
+    void **f32[] = {&w.e32, &w.r32, &w.p32};
     for (void **p : f64)
         if (hipMalloc(p, b64) != hipSuccess) return fail(DWF_ENOMEM, "solver workspace: hipMalloc failed");
     for (void **p : f32)
         if (hipMalloc(p, b32) != hipSuccess) return fail(DWF_ENOMEM, "solver workspace: hipMalloc failed");
     if (hipMalloc(&w.p16, b16) != hipSuccess) return fail(DWF_ENOMEM, "solver workspace: hipMalloc failed");
     if (hipMalloc(&w.full_tmp, 2 * b64) != hipSuccess) return fail(DWF_ENOMEM, "solver workspace: hipMalloc failed");
-    w.bytes = 4 * b64 + 4 * b32 + b16 + 2 * b64;
+    w.bytes = 4 * b64 + 3 * b32 + b16 + 2 * b64;
     return DWF_OK;
 }
 
@@ -180,81 +176,53 @@ static int norm2_sync(dwf_ctx ctx, const void *x, int prec, double *out, hipStre
 }
 
 // Plain CG iterations on A e = r from the current (x, r): p = r, until
-// |r|^2 <= stop_rr or the iteration budget is used.  vprec is the vector
-// precision (F64 or F32); oprec the operator precision (p is additionally
-// kept in oprec when that is a 16-bit format).
-static int cg_core(dwf_ctx ctx, int vprec, int oprec, void *x, void *r, void *p, void *ap, double stop_rr,
-                   int budget, int *iters_out, int *status_out, hipStream_t st) {
+// |r|^2 <= stop_rr or the iteration budget is used.  vprec is the precision of
+// x and r (F64 or F32); oprec the operator's, which p is stored in.
+static int cg_core(dwf_ctx ctx, int vprec, int oprec, void *x, void *r, void *p, double stop_rr, int budget,
+                   int *iters_out, int *status_out, hipStream_t st) {
     const Geom &g = ctx->g;
     const long n = g.half * g.Ls * 12;
-    const long nv = vprec == DWF_F64 ? n : n / 2;
-    const size_t bytes = cb_bytes(g, vprec);
-    const bool sixteen = oprec == DWF_F16 || oprec == DWF_BF16;
-    void *p16 = ctx->work.p16;
+    const unsigned nb = nb256(g.half * g.Ls);
+    u32x4 *x4 = (u32x4 *)x, *p4 = (u32x4 *)p;
+    const u32x4 *r4 = (const u32x4 *)r;
+    double *scal = ctx->scal, *parts = ctx->dhop_partials;
+    void *y = ctx->tmp[1];
     int rc;
-    // |r|^2 -> scal[S_RED] -> scal[S_RR]
-    if ((rc = launch_reduce(ctx->partials, ctx->scal + S_RED, r, nullptr, n, vprec, 0, st))) return rc;
-    hipLaunchKernelGGL(k_set_scalars, 1, 64, 0, st, ctx->scal, stop_rr);
-    DWF_HIP(hipMemcpyAsync(p, r, bytes, hipMemcpyDeviceToDevice, st));
-    if (sixteen) {
-        if (oprec == DWF_F16)
-            hipLaunchKernelGGL((k_convert_scale<DWF_F32, DWF_F16>), nb256(g.half * g.Ls), 256, 0, st, (u32x4 *)p16,
-                               (const u32x4 *)p, 1.0, g.half, g.Ls);
-        else
-            hipLaunchKernelGGL((k_convert_scale<DWF_F32, DWF_BF16>), nb256(g.half * g.Ls), 256, 0, st, (u32x4 *)p16,
-                               (const u32x4 *)p, 1.0, g.half, g.Ls);
-    }
+    // |r|^2 -> scal[S_RED] -> scal[S_RR]; p = r
+    if ((rc = launch_reduce(ctx->partials, scal + S_RED, r, nullptr, n, vprec, 0, st))) return rc;
+    hipLaunchKernelGGL(k_set_scalars, 1, 64, 0, st, scal, stop_rr);
+    if (oprec == vprec) DWF_HIP(hipMemcpyAsync(p, r, cb_bytes(g, vprec), hipMemcpyDeviceToDevice, st));
+    else if ((rc = launch_convert(g, p, oprec, r, vprec, 1, st))) return rc;
     hipEvent_t ev[2] = {(hipEvent_t)ctx->events[0], (hipEvent_t)ctx->events[1]};
     double *hs = ctx->host_scal;
-    int it = 0, status = 0;
-    for (; it < budget; ++it) {
-        // Ap, and <p, A p> = |M_pc p|^2 from the M_pc kernel's workgroup partials -> alpha
-        long nparts = 0;
-        if (vprec == DWF_F64) rc = op_mdagm(ctx, ap, p, DWF_F64, ctx->tmp[1], st, ctx->dhop_partials, &nparts);
-        else if (sixteen) rc = op_mdagm_mixed(ctx, ap, DWF_F32, p16, oprec, st, ctx->dhop_partials, &nparts);
-        else rc = op_mdagm(ctx, ap, p, DWF_F32, ctx->tmp[1], st, ctx->dhop_partials, &nparts);
-        if (rc) return rc;
-        hipLaunchKernelGGL(k_cg_alpha, 1, kRedThreads, 0, st, ctx->scal, ctx->dhop_partials, nparts);
-        // x, r update and |r|^2 -> beta, stop flag
+    for (int it = 0; it < budget; ++it) {
+        long np_y = 0, np_r = 0;
+        if ((rc = op_mpc(ctx, y, p, 0, oprec, st, parts, &np_y))) return rc;
+        hipLaunchKernelGGL(k_cg_alpha, 1, kSumThreads, 0, st, scal, parts, np_y);
+        if ((rc = op_mpcdag_cg(ctx, r, vprec, y, oprec, scal + S_ALPHA, scal + S_LIVE, parts, &np_r, st)))
+            return rc;
+        hipLaunchKernelGGL(k_cg_beta, 1, kSumThreads, 0, st, scal, parts, np_r);
         if (vprec == DWF_F64)
-            hipLaunchKernelGGL(k_cg_xr<DWF_F64>, kRedBlocks, kRedThreads, 0, st, (u32x4 *)x, (u32x4 *)r,
-                               (const u32x4 *)p, (const u32x4 *)ap, ctx->scal, ctx->partials, nv);
-        else
-            hipLaunchKernelGGL(k_cg_xr<DWF_F32>, kRedBlocks, kRedThreads, 0, st, (u32x4 *)x, (u32x4 *)r,
-                               (const u32x4 *)p, (const u32x4 *)ap, ctx->scal, ctx->partials, nv);
-        hipLaunchKernelGGL(k_cg_beta, 1, kRedThreads, 0, st, ctx->scal, ctx->partials);
-        // p = r + beta p
-        const unsigned nb = nb256(g.half * g.Ls);
-        if (vprec == DWF_F64)
-            hipLaunchKernelGGL((k_cg_p<DWF_F64, -1>), nb, 256, 0, st, (u32x4 *)p, (const u32x4 *)r, nullptr,
-                               ctx->scal, g.half, g.Ls);
+            hipLaunchKernelGGL((k_cg_px<DWF_F64, DWF_F64>), nb, 256, 0, st, x4, r4, p4, scal, g.half, g.Ls);
         else if (oprec == DWF_F16)
-            hipLaunchKernelGGL((k_cg_p<DWF_F32, DWF_F16>), nb, 256, 0, st, (u32x4 *)p, (const u32x4 *)r,
-                               (u32x4 *)p16, ctx->scal, g.half, g.Ls);
+            hipLaunchKernelGGL((k_cg_px<DWF_F32, DWF_F16>), nb, 256, 0, st, x4, r4, p4, scal, g.half, g.Ls);
         else if (oprec == DWF_BF16)
-            hipLaunchKernelGGL((k_cg_p<DWF_F32, DWF_BF16>), nb, 256, 0, st, (u32x4 *)p, (const u32x4 *)r,
-                               (u32x4 *)p16, ctx->scal, g.half, g.Ls);
+            hipLaunchKernelGGL((k_cg_px<DWF_F32, DWF_BF16>), nb, 256, 0, st, x4, r4, p4, scal, g.half, g.Ls);
         else
-            hipLaunchKernelGGL((k_cg_p<DWF_F32, -1>), nb, 256, 0, st, (u32x4 *)p, (const u32x4 *)r, nullptr,
-                               ctx->scal, g.half, g.Ls);
+            hipLaunchKernelGGL((k_cg_px<DWF_F32, DWF_F32>), nb, 256, 0, st, x4, r4, p4, scal, g.half, g.Ls);
         DWF_HIP(hipGetLastError());
         // stop flag, read one iteration behind
-        DWF_HIP(hipMemcpyAsync(hs + 8 * (it & 1), ctx->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+        DWF_HIP(hipMemcpyAsync(hs + 8 * (it & 1), scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
         DWF_HIP(hipEventRecord(ev[it & 1], st));
         if (it >= 1) {
             DWF_HIP(hipEventSynchronize(ev[(it - 1) & 1]));
-            if (hs[8 * ((it - 1) & 1) + S_DONE] != 0) {
-                ++it;
-                break;
-            }
+            if (hs[8 * ((it - 1) & 1) + S_DONE] != 0) break;
         }
     }
     DWF_HIP(hipStreamSynchronize(st));
-    DWF_HIP(hipMemcpy(hs, ctx->scal, 8 * sizeof(double), hipMemcpyDeviceToHost));
-    status = (int)hs[S_DONE];
+    DWF_HIP(hipMemcpy(hs, scal, 8 * sizeof(double), hipMemcpyDeviceToHost));
     *iters_out = (int)hs[S_ITERS];
-    *status_out = status;
-    (void)it;
+    *status_out = (int)hs[S_DONE];
     return DWF_OK;
 }
 
@@ -302,8 +270,8 @@ int cg_solve(dwf_ctx ctx, void *x, const void *b, double tol, int maxit, int mod
         s.outer_iters += 1;
         int it = 0, status = 0;
         if (mode == 0) {
-            if ((rc = cg_core(ctx, DWF_F64, DWF_F64, x, w.r64, w.p64, w.ap64, tol * tol * bb, maxit - total, &it,
-                              &status, st)))
+            if ((rc = cg_core(ctx, DWF_F64, DWF_F64, x, w.r64, w.p64, tol * tol * bb, maxit - total, &it, &status,
+                              st)))
                 return rc;
         } else {
             // inner solve A e = r^, r^ = r * sqrt(n)/|r| in FP32 (components of order one)
@@ -312,8 +280,9 @@ int cg_solve(dwf_ctx ctx, void *x, const void *b, double tol, int maxit, int mod
                                (u32x4 *)w.r32, (const u32x4 *)w.r64, scale, g.half, g.Ls);
             DWF_HIP(hipMemsetAsync(w.e32, 0, cb_bytes(g, DWF_F32), st));
             const int budget = std::min(inner_maxit, maxit - total);
-            if ((rc = cg_core(ctx, DWF_F32, oprec, w.e32, w.r32, w.p32, w.ap32,
-                              inner_tol * inner_tol * (double)n, budget, &it, &status, st)))
+            void *p = oprec == DWF_F32 ? w.p32 : w.p16;
+            if ((rc = cg_core(ctx, DWF_F32, oprec, w.e32, w.r32, p, inner_tol * inner_tol * (double)n, budget, &it,
+                              &status, st)))
                 return rc;
             hipLaunchKernelGGL(k_axpy_f32_to_f64, nb256(g.half * g.Ls), 256, 0, st, (u32x4 *)x,
                                (const u32x4 *)w.e32, 1.0 / scale, g.half, g.Ls);
