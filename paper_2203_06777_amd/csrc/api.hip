@@ -66,8 +66,9 @@ static void tune_load_locked() {
     std::string line;
     while (std::getline(f, line)) {
         std::istringstream is(line);
-        int p, d, l0, l1, l2, l3, ls, spb, xcd, spl, rows, ty, tz, tt;
+        int p, d, l0, l1, l2, l3, ls, spb, xcd, spl, rows, ty, tz, tt, occ = 0;
         if (is >> p >> d >> l0 >> l1 >> l2 >> l3 >> ls >> spb >> xcd >> spl >> rows >> ty >> tz >> tt) {
+            if (!(is >> occ)) occ = 0;
             std::ostringstream k;
             k << p << ' ' << d << ' ' << l0 << ' ' << l1 << ' ' << l2 << ' ' << l3 << ' ' << ls;
             DhopShape s;
@@ -78,6 +79,7 @@ static void tune_load_locked() {
             s.ty = ty;
             s.tz = tz;
             s.tt = tt;
+            s.occ = occ;
             g_tune[k.str()] = s;
         }
     }
@@ -131,6 +133,11 @@ int dwf_create(const dwf_geom *geom, dwf_ctx *out) {
         int lds = 0;
         if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) == hipSuccess && lds > 0)
             c->lds_limit = (size_t)lds;
+        int per_cu = 0;
+        if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c->device) ==
+                hipSuccess &&
+            per_cu > 0)
+            c->lds_per_cu = (size_t)per_cu;
     }
     if (std::getenv("DWF_TEST_FAIL_ALLOC")) return cleanup(DWF_ENOMEM, "dwf_create: allocation failure forced");
     for (int p = 0; p < 4; ++p)
@@ -445,19 +452,22 @@ int dwf_tune(dwf_ctx ctx, int prec, int dagger, double *best_us, void *stream) {
         }
     {
         const int per_row = (g.L[0] / 2) * g.Ls;
-        const int tiles[][3] = {{1, 1, 1}, {4, 4, g.L[3]}, {8, 8, g.L[3]}, {4, 4, 8}, {g.L[1], 1, 1}, {2, 2, g.L[3]}};
+        const int tiles[][3] = {{1, 1, 1},     {4, 4, g.L[3]}, {8, 8, g.L[3]}, {4, 8, g.L[3]}, {8, 4, g.L[3]},
+                                {4, 4, 8},     {g.L[1], 1, 1}, {2, 2, g.L[3]}, {2, 4, g.L[3]}};
         for (int rows = 1; rows * per_row <= kMaxDhopThreads; ++rows)
             for (const auto &tl : tiles)
-                for (int xcd : {0, 1}) {
-                    DhopShape s;
-                    s.rows = rows;
-                    s.ty = tl[0];
-                    s.tz = tl[1];
-                    s.tt = tl[2];
-                    s.xcd = xcd;
-                    s.nt_store = 1;
-                    if (row_shape_ok(g, s, prec, ctx->lds_limit)) cand.push_back(s);
-                }
+                for (int xcd : {0, 1})
+                    for (int occ : {0, 2, 3}) {
+                        DhopShape s;
+                        s.rows = rows;
+                        s.ty = tl[0];
+                        s.tz = tl[1];
+                        s.tt = tl[2];
+                        s.xcd = xcd;
+                        s.nt_store = 1;
+                        s.occ = occ;
+                        if (row_shape_ok(g, s, prec, ctx->lds_limit)) cand.push_back(s);
+                    }
     }
     if (cand.empty()) cand.push_back(default_shape(g));
     hipEvent_t e0, e1;
@@ -502,8 +512,9 @@ int dwf_tune(dwf_ctx ctx, int prec, int dagger, double *best_us, void *stream) {
         DWF_HIP(hipEventElapsedTime(&ms, e0, e1));
         const double us = 1000.0 * ms / reps;
         if (std::getenv("DWF_LOG"))
-            std::fprintf(stderr, "[dwf] tune prec=%d dagger=%d nt=%d spb=%d rows=%d tile=%dx%dx%d xcd=%d: %.2f us\n",
-                         prec, dagger, s.nt_store, s.spb, s.rows, s.ty, s.tz, s.tt, s.xcd, us);
+            std::fprintf(stderr,
+                         "[dwf] tune prec=%d dagger=%d nt=%d spb=%d rows=%d tile=%dx%dx%d xcd=%d occ=%d: %.2f us\n",
+                         prec, dagger, s.nt_store, s.spb, s.rows, s.ty, s.tz, s.tt, s.xcd, s.occ, us);
         if (us < best) {
             best = us;
             best_s = s;
@@ -523,7 +534,8 @@ int dwf_tune(dwf_ctx ctx, int prec, int dagger, double *best_us, void *stream) {
             std::ofstream f(path, std::ios::trunc);
             for (auto &kv : g_tune)
                 f << kv.first << ' ' << kv.second.spb << ' ' << kv.second.xcd << ' ' << kv.second.nt_store << ' '
-                  << kv.second.rows << ' ' << kv.second.ty << ' ' << kv.second.tz << ' ' << kv.second.tt << '\n';
+                  << kv.second.rows << ' ' << kv.second.ty << ' ' << kv.second.tz << ' ' << kv.second.tt << ' '
+                  << kv.second.occ << '\n';
         }
     }
     if (best_us) *best_us = best;

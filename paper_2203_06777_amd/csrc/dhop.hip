@@ -30,6 +30,7 @@ struct DhopArgs {
     // row kernel: rows per workgroup, number of rows, traversal tile and its reciprocals
     int rows;
     unsigned nrows, ty, tz, tt, nty, ntt;
+    unsigned lds_pad;  // host side: minimum LDS request of the row kernel (residency cap)
     float inv_per, inv_ty, inv_tz, inv_ntt, inv_ntyt;
     double alpha, beta, d5, mf;
     double *norm_out;
@@ -233,43 +234,62 @@ __global__ void __launch_bounds__(kMaxDhopThreads) k_dhop_rows(const DhopArgs a)
     if constexpr (EPI == EPI_CG)
         if (*a.cg_live == 0) return;  // the solver has stopped: r stays as it is
 
-    // LDS: the rows' link blocks (as stored in global memory), then the input rows
-    const int VX = L0h * NG * Ls;                   // 16-byte vectors per field row
-    const int VL = L0h * 8 * 18 * PT<PI>::RB / 16;  // 16-byte vectors of links per row
-    u32x4 *lds_l = reinterpret_cast<u32x4 *>(smem);
-    u32x4 *lds_x = lds_l + a.rows * VL;
-    for (int rr = 0; rr < a.rows; ++rr) {
-        if (q0 + rr >= a.nrows) break;
-        unsigned y1, y2, y3;  // uniform across the workgroup
-        rowmap(a, q0 + rr, y1, y2, y3);
-        const unsigned prow = y1 + a.lat.L1 * (y2 + a.lat.L2 * y3);
-        const u32x4 *gl = (const u32x4 *)a.links + (size_t)prow * VL;
-        const u32x4 *gx = (const u32x4 *)a.in + (size_t)prow * VX;
-        for (int v = t; v < VL; v += nthr) lds_l[rr * VL + v] = gl[v];
-        for (int v = t; v < VX; v += nthr) lds_x[rr * VX + v] = gx[v];
-    }
-    __syncthreads();
-
+    // lane coordinates and neighbour rows
     const bool active = q0 + r < a.nrows;
     unsigned x1 = 0, x2 = 0, x3 = 0;
     if (active) rowmap(a, q0 + r, x1, x2, x3);
     const long rest = x1 + (long)a.lat.L1 * (x2 + (long)a.lat.L2 * x3);
     const long c = rest * L0h + xh;
+    const unsigned L0 = 2 * a.lat.L0h, L1 = a.lat.L1, L2 = a.lat.L2, L3 = a.lat.L3;
+    const unsigned x0 = 2 * xh + ((a.parity + x1 + x2 + x3) & 1);
+    const int lx0 = (int)((x0 + 1 == L0 ? 0 : x0 + 1) >> 1);
+    const int lx4 = (int)((x0 == 0 ? L0 - 1 : x0 - 1) >> 1);
+    const long s2 = L1, s3 = (long)L1 * L2;
+    const long nb1 = (rest + (x1 + 1 == L1 ? -(long)(L1 - 1) : 1)) * L0h + xh;
+    const long nb5 = (rest + (x1 == 0 ? (long)(L1 - 1) : -1)) * L0h + xh;
+    const long nb2 = (rest + (x2 + 1 == L2 ? -(long)(L2 - 1) * s2 : s2)) * L0h + xh;
+    const long nb6 = (rest + (x2 == 0 ? (long)(L2 - 1) * s2 : -s2)) * L0h + xh;
+    const long nb3 = (rest + (x3 + 1 == L3 ? -(long)(L3 - 1) * s3 : s3)) * L0h + xh;
+    const long nb7 = (rest + (x3 == 0 ? (long)(L3 - 1) * s3 : -s3)) * L0h + xh;
+
+    // LDS: the rows' link blocks (as stored in global memory), then the input rows
+    const int VX = L0h * NG * Ls;                   // 16-byte vectors per field row
+    const int VL = L0h * 8 * 18 * PT<PI>::RB / 16;  // 16-byte vectors of links per row
+    u32x4 *lds_l = reinterpret_cast<u32x4 *>(smem);
+    u32x4 *lds_x = lds_l + a.rows * VL;
+    // Each lane issues up to kStage loads of a row before its first LDS write, so
+    // the copy of a row costs about one memory latency instead of one per vector.
+    constexpr int kStage = 12;
+    const int nrow_here = (int)min((unsigned)a.rows, a.nrows - q0);
+    for (int rr = 0; rr < nrow_here; ++rr) {
+        unsigned y1, y2, y3;  // uniform across the workgroup
+        rowmap(a, q0 + rr, y1, y2, y3);
+        const size_t prow = y1 + a.lat.L1 * (y2 + a.lat.L2 * y3);
+        const u32x4 *gl = (const u32x4 *)a.links + prow * VL;
+        const u32x4 *gx = (const u32x4 *)a.in + prow * VX;
+        u32x4 *dl = lds_l + rr * VL;
+        u32x4 *dx = lds_x + rr * VX;
+        const int n = VL + VX;
+        for (int v0 = t; v0 < n; v0 += kStage * nthr) {
+            u32x4 buf[kStage];
+#pragma unroll
+            for (int u = 0; u < kStage; ++u) {
+                const int v = v0 + u * nthr;
+                if (v < n) buf[u] = *(v < VL ? gl + v : gx + (v - VL));
+            }
+#pragma unroll
+            for (int u = 0; u < kStage; ++u) {
+                const int v = v0 + u * nthr;
+                if (v < n) *(v < VL ? dl + v : dx + (v - VL)) = buf[u];
+            }
+        }
+    }
+    __syncthreads();
+
     A acc[24];
 #pragma unroll
     for (int k = 0; k < 24; ++k) acc[k] = 0;
     if (active) {
-        const unsigned L0 = 2 * a.lat.L0h, L1 = a.lat.L1, L2 = a.lat.L2, L3 = a.lat.L3;
-        const unsigned x0 = 2 * xh + ((a.parity + x1 + x2 + x3) & 1);
-        const int lx0 = (int)((x0 + 1 == L0 ? 0 : x0 + 1) >> 1);
-        const int lx4 = (int)((x0 == 0 ? L0 - 1 : x0 - 1) >> 1);
-        const long s2 = L1, s3 = (long)L1 * L2;
-        const long nb1 = (rest + (x1 + 1 == L1 ? -(long)(L1 - 1) : 1)) * L0h + xh;
-        const long nb5 = (rest + (x1 == 0 ? (long)(L1 - 1) : -1)) * L0h + xh;
-        const long nb2 = (rest + (x2 + 1 == L2 ? -(long)(L2 - 1) * s2 : s2)) * L0h + xh;
-        const long nb6 = (rest + (x2 == 0 ? (long)(L2 - 1) * s2 : -s2)) * L0h + xh;
-        const long nb3 = (rest + (x3 + 1 == L3 ? -(long)(L3 - 1) * s3 : s3)) * L0h + xh;
-        const long nb7 = (rest + (x3 == 0 ? (long)(L3 - 1) * s3 : -s3)) * L0h + xh;
         const char *lk = reinterpret_cast<const char *>(lds_l) + (size_t)(r * L0h + xh) * 8 * 18 * PT<PI>::RB;
         const u32x4 *xr = lds_x + r * VX;
         constexpr int SG = DAG ? 1 : -1;
@@ -360,7 +380,7 @@ DhopShape default_row_shape(const Geom &g, int prec, size_t lds_limit) {
     if (per_row > kMaxDhopThreads) return sh;
     DhopShape r = sh;
     r.rows = std::max(1, 256 / per_row);
-    r.ty = g.L[1] % 4 == 0 ? 4 : 1;
+    r.ty = g.L[1] % 8 == 0 ? 8 : (g.L[1] % 4 == 0 ? 4 : 1);
     r.tz = g.L[2] % 4 == 0 ? 4 : 1;
     r.tt = g.L[3];
     return row_shape_ok(g, r, prec, lds_limit) ? r : sh;
@@ -397,8 +417,9 @@ static int launch_t(const DhopArgs &a, int ls_t, long nblocks, int threads, hipS
     using A = typename PT<PI>::A;
     const dim3 grid((unsigned)nblocks), block(threads);
     if (a.rows > 0) {
-        const size_t shm = std::max(row_lds_bytes(a.rows, (int)a.lat.L0h, a.Ls, PI),
-                                    EPI == EPI_M5INV ? (size_t)threads * 25 * sizeof(A) : (size_t)0);
+        const size_t shm = std::max({row_lds_bytes(a.rows, (int)a.lat.L0h, a.Ls, PI),
+                                     EPI == EPI_M5INV ? (size_t)threads * 25 * sizeof(A) : (size_t)0,
+                                     (size_t)a.lds_pad});
         switch (ls_t) {
             case 8: hipLaunchKernelGGL((k_dhop_rows<PI, PO, DAG, EPI, 8>), grid, block, shm, st, a); break;
             case 12: hipLaunchKernelGGL((k_dhop_rows<PI, PO, DAG, EPI, 12>), grid, block, shm, st, a); break;
@@ -481,6 +502,12 @@ int launch_dhop(dwf_ctx ctx, const DhopCall &c, const DhopShape &shape_in, hipSt
     a.inv_tz = 1.0f / (float)a.tz;
     a.inv_ntt = 1.0f / (float)a.ntt;
     a.inv_ntyt = 1.0f / (float)a.nty;
+    // residency cap: request enough LDS that at most occ workgroups fit on one CU
+    a.lds_pad = 0;
+    if (rows_mode && shape.occ > 0) {
+        const size_t pad = (ctx->lds_per_cu / (size_t)(shape.occ + 1) + 1024) & ~(size_t)255;
+        if (pad <= ctx->lds_limit) a.lds_pad = (unsigned)pad;
+    }
     int threads;
     long nblocks;
     if (rows_mode) {

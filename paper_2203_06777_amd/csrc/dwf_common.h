@@ -63,6 +63,8 @@ struct DhopShape {
     int rows = 0;       // > 0: row kernel with this many whole x-rows per workgroup (links and the
                         //      x-neighbour rows staged in LDS); 0: site kernel
     int ty = 1, tz = 1, tt = 1;  // row kernel: (y, z, t) tile of the row traversal order
+    int occ = 0;        // row kernel: > 0 caps the workgroups resident on one CU at occ (by
+                        //      padding the LDS request), which bounds the rows in flight per L2
 };
 
 constexpr int kMaxDhopThreads = 512;
@@ -114,6 +116,7 @@ struct dwf_ctx_s {
     void *events[2] = {};        // hipEvent_t pair for the solver's lagged stop check
     dwf::DhopShape shape[4][2];  // tuned launch shape per (prec, dagger)
     size_t lds_limit = 65536;    // LDS bytes one workgroup may allocate on this device
+    size_t lds_per_cu = 65536;   // LDS bytes of one compute unit
     double inner_tol = 0.0;
     int inner_maxit = 0;
     dwf::CgWork work;
