@@ -176,8 +176,9 @@ int dwf_force(dwf_ctx ctx, double *F, const void *X, const void *Y, int kind, do
 
 /* A plan applies dwf_dhop (same out_parity, dagger and precision) to nrhs[i]
  * fields of each of nlat contexts (lattices may differ in volume and Ls) in
- * one persistent launch.  The contexts must outlive the plan and have their
- * gauge set.  dwf_batch_capture binds the field pointers (outs / ins list the
+ * one kernel launch (one workgroup per (lattice, field, row block) item, each
+ * lattice with its tuned launch shape).  The contexts must outlive the plan
+ * and have their gauge set; a shape tuned after dwf_batch_plan is not seen.  dwf_batch_capture binds the field pointers (outs / ins list the
  * fields lattice by lattice, sum(nrhs) each) and records the launch into a
  * HIP graph on `stream`; dwf_batch_launch replays it. */
 int dwf_batch_plan(const dwf_ctx *ctxs, int nlat, const int *nrhs, int prec, int dagger, dwf_batch *plan);

@@ -1,16 +1,22 @@
 // Batched hopping term: many right-hand sides of several lattices (of
-// different volumes and Ls) in one persistent launch, recorded as a HIP graph.
+// different volumes and Ls) in one launch, recorded as a HIP graph.
 //
-// Work items are (lattice, tile, rhs) with the RHS index innermost, so the
-// items that share a tile's links run at the same time and the links are
-// read from HBM once for all right-hand sides.  A fixed grid of resident
-// workgroups walks the item list: workgroup b takes one contiguous run of
-// items, and the XCD remap gives each XCD one contiguous part of the list, so
-// neighbouring tiles share that XCD's L2.  The item loop ends for every
-// workgroup after a fixed count, with no queue or atomics.
+// Work items are (lattice, rhs, row block) with the row blocks innermost, and
+// every item runs the row-block body of the single-field kernel (links and
+// x-neighbour rows in LDS, each lattice with its own tuned shape).  Each XCD
+// owns one contiguous eighth of the item list and its workgroups step through
+// it together, so the items in flight on one XCD are neighbouring row blocks of
+// one field and share that XCD's L2.  The grid has one workgroup per item: a
+// resident grid that walks the list (fewer workgroups, several items each) and
+// an order with the RHS innermost (a row block's links shared by all RHS) were
+// both measured slower, since they spread the rows in flight over more fields
+// than L2 holds.  Lattices whose rows do not fit a workgroup fall back to a
+// site-per-lane variant with a resident grid.  The item loops end after a fixed
+// count, with no queue or atomics.
+#include <algorithm>
 #include <vector>
 
-#include "dwf_dhop_core.h"
+#include "dwf_rows.h"
 
 struct dwf_batch_s;
 
@@ -37,6 +43,46 @@ struct BatchDesc {
     BatchLat lat[kMaxBatchLat];
 };
 
+// Row-block items.
+struct BatchRowLat {
+    DhopArgs a;  // geometry, shape and links of the lattice (fields come per item)
+    long item_begin;
+    long nblk;  // row blocks of the lattice
+    int nrhs, rhs_off;
+};
+
+struct BatchRowDesc {
+    int nlat;
+    long total_items;
+    const u32x4 *const *ins;
+    u32x4 *const *outs;
+    BatchRowLat lat[kMaxBatchLat];
+};
+
+constexpr unsigned kXcds = 8;  // workgroup b runs on XCD b % 8
+
+template <int P, int DAG, int LS>
+__global__ void __launch_bounds__(kMaxDhopThreads) k_dhop_batch_rows(const BatchRowDesc *__restrict__ d) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const unsigned x = blockIdx.x % kXcds, w = blockIdx.x / kXcds, nw = gridDim.x / kXcds;
+    const long chunk = (d->total_items + kXcds - 1) / kXcds;
+    const long begin = (long)x * chunk;
+    const long end = begin + chunk < d->total_items ? begin + chunk : d->total_items;
+    for (long item = begin + w; item < end; item += nw) {
+        int l = 0;
+        while (l + 1 < d->nlat && item >= d->lat[l + 1].item_begin) ++l;
+        const BatchRowLat &L = d->lat[l];
+        const long local = item - L.item_begin;
+        const int rhs = (int)(local / L.nblk);
+        const long blk = local - (long)rhs * L.nblk;
+        row_block<P, P, DAG, EPI_SCALE, LS>(L.a, (unsigned)blk * (unsigned)L.a.rows,
+                                            (const char *)d->ins[L.rhs_off + rhs], (char *)d->outs[L.rhs_off + rhs],
+                                            smem);
+        __syncthreads();  // the next item stages its rows into the same LDS
+    }
+}
+
+// Site items (fallback).
 template <int P, int DAG>
 __global__ void __launch_bounds__(kMaxDhopThreads) k_dhop_batch(const BatchDesc *__restrict__ d) {
     using A = typename PT<P>::A;
@@ -72,10 +118,15 @@ using namespace dwf;
 struct dwf_batch_s {
     std::vector<dwf_ctx> ctxs;
     std::vector<int> nrhs;
-    int prec = 0, dagger = 0, nlat = 0, total_rhs = 0, threads = 0;
+    std::vector<DhopShape> shapes;
+    int prec = 0, dagger = 0, nlat = 0, total_rhs = 0, threads = 0, ls_t = 0;
+    bool rows = false;
+    size_t lds = 0;
     long nblocks = 0;
     BatchDesc host{};
     BatchDesc *dev = nullptr;
+    BatchRowDesc rhost{};
+    BatchRowDesc *rdev = nullptr;
     void **ptrs = nullptr;  // device: ins[total_rhs], outs[total_rhs]
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -92,11 +143,89 @@ static const void *batch_kernel(int prec, int dagger) {
     }
 }
 
+template <int P>
+static const void *batch_rows_kernel_p(int dagger, int ls_t) {
+    switch (ls_t) {
+        case 8: return dagger ? (const void *)k_dhop_batch_rows<P, 1, 8> : (const void *)k_dhop_batch_rows<P, 0, 8>;
+        case 12: return dagger ? (const void *)k_dhop_batch_rows<P, 1, 12> : (const void *)k_dhop_batch_rows<P, 0, 12>;
+        case 16: return dagger ? (const void *)k_dhop_batch_rows<P, 1, 16> : (const void *)k_dhop_batch_rows<P, 0, 16>;
+        default: return dagger ? (const void *)k_dhop_batch_rows<P, 1, 0> : (const void *)k_dhop_batch_rows<P, 0, 0>;
+    }
+}
+
+static const void *batch_rows_kernel(int prec, int dagger, int ls_t) {
+    switch (prec) {
+        case DWF_F64: return batch_rows_kernel_p<DWF_F64>(dagger, ls_t);
+        case DWF_F32: return batch_rows_kernel_p<DWF_F32>(dagger, ls_t);
+        case DWF_F16: return batch_rows_kernel_p<DWF_F16>(dagger, ls_t);
+        default: return batch_rows_kernel_p<DWF_BF16>(dagger, ls_t);
+    }
+}
+
+// Row-block plan: every lattice must have a row shape that fits one workgroup.
+static bool plan_rows(dwf_batch p, const dwf_ctx *ctxs, int nlat, const int *nrhs) {
+    int threads = 0, ls_common = ctxs[0]->g.Ls;
+    size_t lds = 0, big = 0;
+    long items = 0;
+    int rhs_off = 0;
+    for (int l = 0; l < nlat; ++l) {
+        dwf_ctx c = ctxs[l];
+        const Geom &g = c->g;
+        DhopShape sh = c->shape[p->prec][p->dagger];
+        if (sh.rows <= 0 || !row_shape_ok(g, sh, p->prec, c->lds_limit)) sh = default_row_shape(g, p->prec, c->lds_limit);
+        if (sh.rows <= 0 || !row_shape_ok(g, sh, p->prec, c->lds_limit)) return false;
+        BatchRowLat &L = p->rhost.lat[l];
+        if (!fill_dhop_args(c, sh, p->prec, 0, L.a)) return false;
+        threads = std::max(threads, sh.rows * (g.L[0] / 2) * g.Ls);
+        lds = std::max(lds, row_lds_bytes(sh.rows, g.L[0] / 2, g.Ls, p->prec));
+        big = std::max(big, cb_bytes(g, p->prec));
+        if (g.Ls != ls_common) ls_common = 0;
+        L.item_begin = items;
+        L.nrhs = nrhs[l];
+        L.rhs_off = rhs_off;
+        L.nblk = (long)((L.a.nrows + sh.rows - 1) / sh.rows);
+        items += L.nblk * nrhs[l];
+        rhs_off += nrhs[l];
+        p->shapes.push_back(sh);
+    }
+    if (lds > ctxs[0]->lds_limit) return false;
+    p->rows = true;
+    p->threads = threads;
+    p->lds = lds;
+    p->ls_t = (big < (size_t(1) << 32) && (ls_common == 8 || ls_common == 12 || ls_common == 16)) ? ls_common : 0;
+    p->rhost.nlat = nlat;
+    p->rhost.total_items = items;
+    p->total_rhs = rhs_off;
+    return true;
+}
+
 int batch_plan(const dwf_ctx *ctxs, int nlat, const int *nrhs, int prec, int dagger, dwf_batch *out) {
     dwf_batch p = new dwf_batch_s();
     p->prec = prec;
     p->dagger = dagger;
     p->nlat = nlat;
+    for (int l = 0; l < nlat; ++l) {
+        p->ctxs.push_back(ctxs[l]);
+        p->nrhs.push_back(nrhs[l]);
+    }
+    if (plan_rows(p, ctxs, nlat, nrhs)) {
+        // one workgroup per item, rounded up to a multiple of the XCD count
+        p->nblocks = (p->rhost.total_items + kXcds - 1) / kXcds * kXcds;
+        if (hipMalloc(&p->rdev, sizeof(BatchRowDesc)) != hipSuccess ||
+            hipMalloc(&p->ptrs, sizeof(void *) * 2 * (size_t)p->total_rhs) != hipSuccess) {
+            (void)hipFree(p->rdev);
+            delete p;
+            return fail(DWF_ENOMEM, "dwf_batch_plan: hipMalloc failed");
+        }
+        p->rhost.ins = (const u32x4 *const *)p->ptrs;
+        p->rhost.outs = (u32x4 *const *)(p->ptrs + p->total_rhs);
+        *out = p;
+        return DWF_OK;
+    }
+    p->ctxs.clear();
+    p->nrhs.clear();
+    p->shapes.clear();
+    p->rows = false;
     int threads = 0;
     for (int l = 0; l < nlat; ++l) {
         const Geom &g = ctxs[l]->g;
@@ -141,7 +270,7 @@ int batch_plan(const dwf_ctx *ctxs, int nlat, const int *nrhs, int prec, int dag
     p->host.per_block = (items + nb - 1) / nb;
     if (hipMalloc(&p->dev, sizeof(BatchDesc)) != hipSuccess ||
         hipMalloc(&p->ptrs, sizeof(void *) * 2 * (size_t)p->total_rhs) != hipSuccess) {
-        hipFree(p->dev);
+        (void)hipFree(p->dev);
         delete p;
         return fail(DWF_ENOMEM, "dwf_batch_plan: hipMalloc failed");
     }
@@ -157,28 +286,37 @@ int batch_capture(dwf_batch p, void *const *outs, const void *const *ins, int ou
         host[r] = const_cast<void *>(ins[r]);
         host[p->total_rhs + r] = outs[r];
     }
-    for (int l = 0; l < p->nlat; ++l) p->host.lat[l].links = p->ctxs[l]->links[p->prec][out_parity];
-    p->host.parity = out_parity;
     DWF_HIP(hipMemcpyAsync(p->ptrs, host.data(), host.size() * sizeof(void *), hipMemcpyHostToDevice, st));
-    DWF_HIP(hipMemcpyAsync(p->dev, &p->host, sizeof(BatchDesc), hipMemcpyHostToDevice, st));
+    if (p->rows) {
+        for (int l = 0; l < p->nlat; ++l)
+            fill_dhop_args(p->ctxs[l], p->shapes[l], p->prec, out_parity, p->rhost.lat[l].a);
+        DWF_HIP(hipMemcpyAsync(p->rdev, &p->rhost, sizeof(BatchRowDesc), hipMemcpyHostToDevice, st));
+    } else {
+        for (int l = 0; l < p->nlat; ++l) p->host.lat[l].links = p->ctxs[l]->links[p->prec][out_parity];
+        p->host.parity = out_parity;
+        DWF_HIP(hipMemcpyAsync(p->dev, &p->host, sizeof(BatchDesc), hipMemcpyHostToDevice, st));
+    }
     DWF_HIP(hipStreamSynchronize(st));
     if (p->exec) {
-        hipGraphExecDestroy(p->exec);
+        (void)hipGraphExecDestroy(p->exec);
         p->exec = nullptr;
     }
     if (p->graph) {
-        hipGraphDestroy(p->graph);
+        (void)hipGraphDestroy(p->graph);
         p->graph = nullptr;
     }
     DWF_HIP(hipGraphCreate(&p->graph, 0));
     hipKernelNodeParams kp{};
     const BatchDesc *arg = p->dev;
+    const BatchRowDesc *rarg = p->rdev;
     void *args[] = {(void *)&arg};
-    kp.func = const_cast<void *>(batch_kernel(p->prec, p->dagger));
+    void *rargs[] = {(void *)&rarg};
+    kp.func = const_cast<void *>(p->rows ? batch_rows_kernel(p->prec, p->dagger, p->ls_t)
+                                         : batch_kernel(p->prec, p->dagger));
     kp.gridDim = dim3((unsigned)p->nblocks);
     kp.blockDim = dim3((unsigned)p->threads);
-    kp.sharedMemBytes = 0;
-    kp.kernelParams = args;
+    kp.sharedMemBytes = (unsigned)p->lds;
+    kp.kernelParams = p->rows ? rargs : args;
     kp.extra = nullptr;
     hipGraphNode_t node;
     DWF_HIP(hipGraphAddKernelNode(&node, p->graph, nullptr, 0, &kp));
@@ -193,10 +331,11 @@ int batch_launch(dwf_batch p, hipStream_t st) {
 }
 
 int batch_free(dwf_batch p) {
-    if (p->exec) hipGraphExecDestroy(p->exec);
-    if (p->graph) hipGraphDestroy(p->graph);
-    hipFree(p->dev);
-    hipFree(p->ptrs);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    (void)hipFree(p->dev);
+    (void)hipFree(p->rdev);
+    (void)hipFree(p->ptrs);
     delete p;
     return DWF_OK;
 }
