@@ -31,8 +31,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_2203_06777_amd/csrc/dhop.hip", "paper_2203_06777_amd/csrc/dwf_dhop_core.h",
-                  "paper_2203_06777_amd/csrc/dwf_device.h", "paper_2203_06777_amd/csrc/dwf_spin.h"]
+KERNEL_SOURCES = ["paper_2203_06777_amd/csrc/dhop.hip", "paper_2203_06777_amd/csrc/dwf_rows.h",
+                  "paper_2203_06777_amd/csrc/dwf_dhop_core.h", "paper_2203_06777_amd/csrc/dwf_device.h",
+                  "paper_2203_06777_amd/csrc/dwf_spin.h", "paper_2203_06777_amd/csrc/dwf_common.h"]
 
 
 def log(msg):
@@ -212,22 +213,18 @@ def main():
         from oracle import coracle as C
 
         nthreads = C.num_threads()
-        probe = 4096
-        C.dhop_cb(u, psi, 1, 0, rows=(0, probe))  # warm-up (threads, first-touch pages)
+        C.dhop_cb(u, psi, 1, 0, rows=(0, 4096))  # warm-up (threads, first-touch pages)
+        # whole applies of the oracle (each call as it stands) until about cpu_seconds have passed
+        nrow, passes = vol // 2, 0
         t = time.time()
-        C.dhop_cb(u, psi, 1, 0, rows=(0, probe))
-        dt = max(time.time() - t, 1e-3)
-        # rows for about cpu_seconds of work: a prefix of the output rows, or whole applies repeated
-        want = max(probe, int(probe * args.cpu_seconds / dt))
-        nrow, passes = (want, 1) if want < vol // 2 else (vol // 2, max(1, round(want / (vol // 2))))
-        t = time.time()
-        for _ in range(passes):
-            C.dhop_cb(u, psi, 1, 0, rows=(0, nrow))
+        while passes == 0 or time.time() - t < args.cpu_seconds:
+            C.dhop_cb(u, psi, 1, 0)
+            passes += 1
         dt = time.time() - t
         cpu = {"value": round(1320.0 * ls * nrow * passes / dt / 1e9, 3), "unit": "GFlop/s", "cores": nthreads,
                "kind": "oracle",
-               "sample": f"plain C FP64 Dhop_cb (oracle) on the 32^4x16 input: output rows 0..{nrow} of "
-                         f"{vol // 2}, {passes} pass(es), {dt:.1f} s"}
+               "sample": f"plain C FP64 Dhop_cb (oracle) on the 32^4x16 input: {passes} whole applies "
+                         f"({nrow} output rows each), {dt:.1f} s"}
         log(f"cpu oracle: {cpu}")
     op.close()
     del u, psi
