@@ -44,8 +44,14 @@ struct BatchDesc {
 };
 
 // Row-block items.
+// Pointers the kernel dereferences are typed as global memory: read from this
+// descriptor as plain pointers they would be accessed with flat instructions.
+typedef const __attribute__((address_space(1))) char *gconst_ptr;
+typedef __attribute__((address_space(1))) char *gptr;
+
 struct BatchRowLat {
-    DhopArgs a;  // geometry, shape and links of the lattice (fields come per item)
+    DhopArgs a;  // geometry and shape of the lattice (fields and links come per item)
+    gconst_ptr links;
     long item_begin;
     long nblk;  // row blocks of the lattice
     int nrhs, rhs_off;
@@ -54,8 +60,8 @@ struct BatchRowLat {
 struct BatchRowDesc {
     int nlat;
     long total_items;
-    const u32x4 *const *ins;
-    u32x4 *const *outs;
+    const gconst_ptr *ins;
+    const gptr *outs;
     BatchRowLat lat[kMaxBatchLat];
 };
 
@@ -75,9 +81,8 @@ __global__ void __launch_bounds__(kMaxDhopThreads) k_dhop_batch_rows(const Batch
         const long local = item - L.item_begin;
         const int rhs = (int)(local / L.nblk);
         const long blk = local - (long)rhs * L.nblk;
-        row_block<P, P, DAG, EPI_SCALE, LS>(L.a, (unsigned)blk * (unsigned)L.a.rows,
-                                            (const char *)d->ins[L.rhs_off + rhs], (char *)d->outs[L.rhs_off + rhs],
-                                            smem);
+        row_block<P, P, DAG, EPI_SCALE, LS>(L.a, (unsigned)blk * (unsigned)L.a.rows, (const char *)d->ins[L.rhs_off + rhs],
+                                            (char *)d->outs[L.rhs_off + rhs], (const char *)L.links, smem);
         __syncthreads();  // the next item stages its rows into the same LDS
     }
 }
@@ -217,8 +222,8 @@ int batch_plan(const dwf_ctx *ctxs, int nlat, const int *nrhs, int prec, int dag
             delete p;
             return fail(DWF_ENOMEM, "dwf_batch_plan: hipMalloc failed");
         }
-        p->rhost.ins = (const u32x4 *const *)p->ptrs;
-        p->rhost.outs = (u32x4 *const *)(p->ptrs + p->total_rhs);
+        p->rhost.ins = (const gconst_ptr *)p->ptrs;
+        p->rhost.outs = (const gptr *)(p->ptrs + p->total_rhs);
         *out = p;
         return DWF_OK;
     }
@@ -288,8 +293,11 @@ int batch_capture(dwf_batch p, void *const *outs, const void *const *ins, int ou
     }
     DWF_HIP(hipMemcpyAsync(p->ptrs, host.data(), host.size() * sizeof(void *), hipMemcpyHostToDevice, st));
     if (p->rows) {
-        for (int l = 0; l < p->nlat; ++l)
-            fill_dhop_args(p->ctxs[l], p->shapes[l], p->prec, out_parity, p->rhost.lat[l].a);
+        for (int l = 0; l < p->nlat; ++l) {
+            BatchRowLat &L = p->rhost.lat[l];
+            fill_dhop_args(p->ctxs[l], p->shapes[l], p->prec, out_parity, L.a);
+            L.links = (gconst_ptr)L.a.links;
+        }
         DWF_HIP(hipMemcpyAsync(p->rdev, &p->rhost, sizeof(BatchRowDesc), hipMemcpyHostToDevice, st));
     } else {
         for (int l = 0; l < p->nlat; ++l) p->host.lat[l].links = p->ctxs[l]->links[p->prec][out_parity];

@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(kMaxDhopThreads) k_dhop_rows(const DhopArgs a)
     if constexpr (EPI == EPI_CG)
         if (*a.cg_live == 0) return;  // the solver has stopped: r stays as it is
     const long lb = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (long)blockIdx.x;
-    row_block<PI, PO, DAG, EPI, LS>(a, (unsigned)lb * (unsigned)a.rows, a.in, a.out, smem);
+    row_block<PI, PO, DAG, EPI, LS>(a, (unsigned)lb * (unsigned)a.rows, a.in, a.out, a.links, smem);
 }
 
 size_t row_lds_bytes(int rows, int L0h, int Ls, int prec) {

@@ -158,7 +158,8 @@ __device__ __forceinline__ void rowmap(const DhopArgs &a, unsigned q, unsigned &
 // (and threads * 25 reals for EPI_M5INV).
 template <int PI, int PO, int DAG, int EPI, int LS>
 __device__ __forceinline__ void row_block(const DhopArgs &a, unsigned q0, const char *__restrict__ in_f,
-                                          char *__restrict__ out_f, unsigned char *smem) {
+                                          char *__restrict__ out_f, const char *__restrict__ links_g,
+                                          unsigned char *smem) {
     using A = typename PT<PI>::A;
     using Off = typename std::conditional<(LS > 0), unsigned, long>::type;
     constexpr int G = PT<PI>::G, NG = 12 / G, R2 = 2 * G;
@@ -176,51 +177,55 @@ __device__ __forceinline__ void row_block(const DhopArgs &a, unsigned q0, const 
     const bool active = t < nthr && q0 + r < a.nrows;
     unsigned x1 = 0, x2 = 0, x3 = 0;
     if (active) rowmap(a, q0 + r, x1, x2, x3);
-    const long rest = x1 + (long)a.lat.L1 * (x2 + (long)a.lat.L2 * x3);
-    const long c = rest * L0h + xh;
+    // row indices in the offset type (32-bit when every field is below 4 GiB; the
+    // wrap-around steps are exact in modular arithmetic)
     const unsigned L0 = 2 * a.lat.L0h, L1 = a.lat.L1, L2 = a.lat.L2, L3 = a.lat.L3;
+    const Off rest = (Off)x1 + (Off)L1 * ((Off)x2 + (Off)L2 * (Off)x3);
+    const Off c = rest * (Off)L0h + (Off)xh;
     const unsigned x0 = 2 * xh + ((a.parity + x1 + x2 + x3) & 1);
     const int lx0 = (int)((x0 + 1 == L0 ? 0 : x0 + 1) >> 1);
     const int lx4 = (int)((x0 == 0 ? L0 - 1 : x0 - 1) >> 1);
-    const long s2 = L1, s3 = (long)L1 * L2;
-    const long nb1 = (rest + (x1 + 1 == L1 ? -(long)(L1 - 1) : 1)) * L0h + xh;
-    const long nb5 = (rest + (x1 == 0 ? (long)(L1 - 1) : -1)) * L0h + xh;
-    const long nb2 = (rest + (x2 + 1 == L2 ? -(long)(L2 - 1) * s2 : s2)) * L0h + xh;
-    const long nb6 = (rest + (x2 == 0 ? (long)(L2 - 1) * s2 : -s2)) * L0h + xh;
-    const long nb3 = (rest + (x3 + 1 == L3 ? -(long)(L3 - 1) * s3 : s3)) * L0h + xh;
-    const long nb7 = (rest + (x3 == 0 ? (long)(L3 - 1) * s3 : -s3)) * L0h + xh;
+    const Off s2 = L1, s3 = (Off)L1 * L2, o0 = 0;
+    const Off nb1 = (rest + (x1 + 1 == L1 ? o0 - (Off)(L1 - 1) : (Off)1)) * (Off)L0h + (Off)xh;
+    const Off nb5 = (rest + (x1 == 0 ? (Off)(L1 - 1) : o0 - 1)) * (Off)L0h + (Off)xh;
+    const Off nb2 = (rest + (x2 + 1 == L2 ? o0 - (Off)(L2 - 1) * s2 : s2)) * (Off)L0h + (Off)xh;
+    const Off nb6 = (rest + (x2 == 0 ? (Off)(L2 - 1) * s2 : o0 - s2)) * (Off)L0h + (Off)xh;
+    const Off nb3 = (rest + (x3 + 1 == L3 ? o0 - (Off)(L3 - 1) * s3 : s3)) * (Off)L0h + (Off)xh;
+    const Off nb7 = (rest + (x3 == 0 ? (Off)(L3 - 1) * s3 : o0 - s3)) * (Off)L0h + (Off)xh;
 
     // LDS: the rows' link blocks (as stored in global memory), then the input rows
     const int VX = L0h * NG * Ls;                   // 16-byte vectors per field row
     const int VL = L0h * 8 * 18 * PT<PI>::RB / 16;  // 16-byte vectors of links per row
     u32x4 *lds_l = reinterpret_cast<u32x4 *>(smem);
     u32x4 *lds_x = lds_l + a.rows * VL;
-    // Each lane issues up to kStage loads of a row before its first LDS write, so
-    // the copy of a row costs about one memory latency instead of one per vector.
-    constexpr int kStage = 12;
+    // Each lane issues its first kL link and kX row loads (branch-free, clamped
+    // index) before its first LDS write, so the copy of a row costs about one
+    // memory latency instead of one per vector; kL, kX cover the common shapes and
+    // larger rows finish in a plain loop.
+    constexpr int kL = PI == DWF_F64 ? 5 : (PI == DWF_F32 ? 3 : 2);
+    constexpr int kX = PI == DWF_F64 ? 12 : (PI == DWF_F32 ? 6 : 3);
     const int nrow_here = (int)min((unsigned)a.rows, a.nrows - q0);
     for (int rr = 0; rr < nrow_here && t < nthr; ++rr) {
         unsigned y1, y2, y3;  // uniform across the workgroup
         rowmap(a, q0 + rr, y1, y2, y3);
         const size_t prow = y1 + a.lat.L1 * (y2 + a.lat.L2 * y3);
-        const u32x4 *gl = (const u32x4 *)a.links + prow * VL;
+        const u32x4 *gl = (const u32x4 *)links_g + prow * VL;
         const u32x4 *gx = (const u32x4 *)in_f + prow * VX;
         u32x4 *dl = lds_l + rr * VL;
         u32x4 *dx = lds_x + rr * VX;
-        const int n = VL + VX;
-        for (int v0 = t; v0 < n; v0 += kStage * nthr) {
-            u32x4 buf[kStage];
+        u32x4 bl[kL], bx[kX];
 #pragma unroll
-            for (int u = 0; u < kStage; ++u) {
-                const int v = v0 + u * nthr;
-                if (v < n) buf[u] = *(v < VL ? gl + v : gx + (v - VL));
-            }
+        for (int u = 0; u < kL; ++u) bl[u] = gl[min(t + u * nthr, VL - 1)];
 #pragma unroll
-            for (int u = 0; u < kStage; ++u) {
-                const int v = v0 + u * nthr;
-                if (v < n) *(v < VL ? dl + v : dx + (v - VL)) = buf[u];
-            }
-        }
+        for (int u = 0; u < kX; ++u) bx[u] = gx[min(t + u * nthr, VX - 1)];
+#pragma unroll
+        for (int u = 0; u < kL; ++u)
+            if (t + u * nthr < VL) dl[t + u * nthr] = bl[u];
+#pragma unroll
+        for (int u = 0; u < kX; ++u)
+            if (t + u * nthr < VX) dx[t + u * nthr] = bx[u];
+        for (int v = t + kL * nthr; v < VL; v += nthr) dl[v] = gl[v];
+        for (int v = t + kX * nthr; v < VX; v += nthr) dx[v] = gx[v];
     }
     __syncthreads();
 
