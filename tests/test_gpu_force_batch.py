@@ -166,6 +166,40 @@ def test_batched_mixed_lattices_match_single_applies_and_oracle():
         D().dwf_batch_free(plan)
 
 
+@pytest.mark.parametrize("prec,dagger,lattices", [
+    ("f64", 1, [((4, 4, 4, 4), 8, 2), ((6, 4, 4, 4), 12, 3)]),          # mixed Ls: generic-Ls row blocks
+    ("f16", 0, [((4, 4, 4, 4), 8, 1), ((8, 4, 2, 6), 4, 2)]),
+    ("bf16", 1, [((4, 4, 4, 4), 8, 2), ((64, 2, 2, 2), 20, 2)]),        # a 640-lane row: site fallback
+])
+def test_batched_precisions_mixed_ls_and_fallback_equal_single_applies(prec, dagger, lattices):
+    """Every field of a batch equals the single-field dwf_dhop bit for bit (same arithmetic order)."""
+    ctxs, ins, outs, nrhs = [], [], [], []
+    for i, (dims, ls, nr) in enumerate(lattices):
+        op, _ = make(dims, ls, 0.5, 900 + i)
+        ctxs.append(op)
+        nrhs.append(nr)
+        for r in range(nr):
+            ins.append(op.pack(to_dev(F.fermion_cb(dims, ls, 950 + 10 * i + r)), 1, prec))
+            outs.append(op.zeros(prec))
+    plan = D().dwf_batch_plan([c.handle for c in ctxs], nrhs, prec, dagger)
+    try:
+        D().dwf_batch_capture(plan, outs, ins, 0)
+        D().dwf_batch_launch(plan)
+        D().dwf_batch_launch(plan)
+        torch.cuda.synchronize()
+        k = 0
+        for li, op in enumerate(ctxs):
+            for _ in range(nrhs[li]):
+                single = op.zeros(prec)
+                D().dwf_dhop(op.handle, single, ins[k], 0, dagger, prec)
+                torch.cuda.synchronize()
+                assert torch.equal(outs[k], single), (li, k)
+                assert float(outs[k].float().abs().sum()) > 0
+                k += 1
+    finally:
+        D().dwf_batch_free(plan)
+
+
 def test_batched_multi_rhs_sampled_32x32x32x32_ls12():
     """12 right-hand sides on 32^4 x 12 (the batched workload): sampled rows of each RHS vs the oracle."""
     w = F.WORKLOADS["batch_32^4x12x12"]
