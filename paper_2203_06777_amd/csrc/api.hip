@@ -113,6 +113,8 @@ int dwf_create(const dwf_geom *geom, dwf_ctx *out) {
     CHECK(geom->Ls >= 1 && geom->Ls <= kMaxLs, "dwf_create: Ls must be in [1, 64]");
     CHECK(std::isfinite(geom->M5) && std::isfinite(geom->mf), "dwf_create: M5 and mf must be finite");
     CHECK(std::fabs(5.0 - geom->M5) > 1e-12, "dwf_create: M5 = 5 makes M5op singular");
+    CHECK(std::fabs(1.0 + geom->mf * std::pow(5.0 - geom->M5, -(double)geom->Ls)) > 1e-12,
+          "dwf_create: 1 + mf (5 - M5)^-Ls = 0 makes M5op singular");
     const long vol = (long)geom->dims[0] * geom->dims[1] * geom->dims[2] * geom->dims[3];
     CHECK(vol / 2 < (1L << 24), "dwf_create: lattice too large (V/2 must be below 2^24 sites)");
     dwf_ctx c = new (std::nothrow) dwf_ctx_s();

@@ -60,6 +60,23 @@ def test_create_rejects_bad_geometry_without_a_device(dims, ls):
     assert "dwf_create" in str(e.value)
 
 
+@pytest.mark.parametrize("dims,ls,M5,mf,what", [
+    ((256, 256, 256, 2), 8, 1.8, 0.01, "too large"),        # V/2 = 2^24 sites
+    ((4, 4, 4, 4), 8, 5.0, 0.01, "singular"),                # 5 - M5 = 0
+    ((4, 4, 4, 4), 2, 3.0, -4.0, "singular"),                # 1 + mf (5 - M5)^-Ls = 0
+    ((4, 4, 4, 4), 8, 1.8, float("nan"), "finite"),
+    ((4, 4, 4, 4), 8, float("inf"), 0.01, "finite"),
+])
+def test_create_rejects_degenerate_parameters_without_a_device(dims, ls, M5, mf, what):
+    from paper_2203_06777_amd import dwf
+
+    lib()
+    with pytest.raises(dwf.DwfError) as e:
+        dwf.dwf_create(dims, ls, M5, mf)
+    assert e.value.code == -1
+    assert what in str(e.value)
+
+
 def test_null_context_is_an_error():
     from paper_2203_06777_amd import dwf
 
