@@ -52,42 +52,6 @@ __device__ __forceinline__ void store_spinor_off(char *__restrict__ base, Off of
     }
 }
 
-template <int P> __device__ __forceinline__ void load_link_nt(const char *links, long c, int dir,
-                                                              typename PT<P>::A *w);
-template <> __device__ __forceinline__ void load_link_nt<DWF_F64>(const char *links, long c, int dir, double *w) {
-    const u32x4 *p = (const u32x4 *)links + (c * 8 + dir) * 9;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) unpack16<DWF_F64>(__builtin_nontemporal_load(p + k), w + 2 * k);
-}
-template <> __device__ __forceinline__ void load_link_nt<DWF_F32>(const char *links, long c, int dir, float *w) {
-    const u32x2 *p = (const u32x2 *)links + (c * 8 + dir) * 9;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const u32x2 r = __builtin_nontemporal_load(p + k);
-        const unsigned re = r.x, im = r.y;
-        w[2 * k] = __builtin_bit_cast(float, re);
-        w[2 * k + 1] = __builtin_bit_cast(float, im);
-    }
-}
-template <> __device__ __forceinline__ void load_link_nt<DWF_F16>(const char *links, long c, int dir, float *w) {
-    const unsigned *p = (const unsigned *)links + (c * 8 + dir) * 9;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const unsigned r = __builtin_nontemporal_load(p + k);
-        w[2 * k] = f16_bits_to_f32((unsigned short)(r & 0xffffu));
-        w[2 * k + 1] = f16_bits_to_f32((unsigned short)(r >> 16));
-    }
-}
-template <> __device__ __forceinline__ void load_link_nt<DWF_BF16>(const char *links, long c, int dir, float *w) {
-    const unsigned *p = (const unsigned *)links + (c * 8 + dir) * 9;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const unsigned r = __builtin_nontemporal_load(p + k);
-        w[2 * k] = bf16_bits_to_f32((unsigned short)(r & 0xffffu));
-        w[2 * k + 1] = bf16_bits_to_f32((unsigned short)(r >> 16));
-    }
-}
-
 // Byte offset of vector (row, group 0, s) in a field with NG groups per row.
 template <int P, typename Off>
 __device__ __forceinline__ Off spinor_off(long row, int Ls, int s) {
