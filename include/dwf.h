@@ -189,10 +189,15 @@ int dwf_batch_free(dwf_batch plan);
 /* ---- autotuning --------------------------------------------------------------- */
 
 /* Times the launch shapes of the hopping kernel for (prec, dagger) on this
- * context's lattice and keeps the fastest; the choice is cached in memory and,
- * if the environment variable DWF_TUNE_CACHE names a file, on disk.  *best_us
- * (host, may be NULL) receives the best time per apply.  Scratch fields are
- * allocated and freed inside. Synchronises the stream. */
+ * context's lattice and keeps the fastest, separately for plain dwf_dhop
+ * launches and for the fused Schur-operator kernels (M5op^-1 and M5op
+ * epilogues, as used by dwf_mpc, dwf_mdagm, dwf_cg and dwf_solve).  Every
+ * candidate must reproduce the first one's output bit for bit (DWF_EHIP
+ * otherwise).  The choices are cached in memory and, if the environment
+ * variable DWF_TUNE_CACHE names a file, on disk.  *best_us (host, may be NULL)
+ * receives the best plain time per apply.  Scratch fields are allocated and
+ * freed inside; the context's temporaries are overwritten.  Synchronises the
+ * stream. */
 int dwf_tune(dwf_ctx ctx, int prec, int dagger, double *best_us, void *stream);
 
 #ifdef __cplusplus

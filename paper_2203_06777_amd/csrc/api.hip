@@ -51,9 +51,10 @@ static std::mutex g_tune_mu;
 static std::map<std::string, DhopShape> g_tune;
 static bool g_tune_loaded = false;
 
-static std::string tune_key(const Geom &g, int prec, int dagger) {
+// Cache key; the second field is dagger + 2 * family (0: plain hopping launch, 1: fused Schur pair).
+static std::string tune_key(const Geom &g, int prec, int dagger, int family) {
     std::ostringstream k;
-    k << prec << ' ' << dagger << ' ' << g.L[0] << ' ' << g.L[1] << ' ' << g.L[2] << ' ' << g.L[3] << ' ' << g.Ls;
+    k << prec << ' ' << dagger + 2 * family << ' ' << g.L[0] << ' ' << g.L[1] << ' ' << g.L[2] << ' ' << g.L[3] << ' ' << g.Ls;
     return k.str();
 }
 
@@ -90,8 +91,11 @@ static void apply_tuned(dwf_ctx ctx) {
     tune_load_locked();
     for (int p = 0; p < 4; ++p)
         for (int d = 0; d < 2; ++d) {
-            auto it = g_tune.find(tune_key(ctx->g, p, d));
-            ctx->shape[p][d] = it != g_tune.end() ? it->second : default_row_shape(ctx->g, p, ctx->lds_limit);
+            const DhopShape def = default_row_shape(ctx->g, p, ctx->lds_limit);
+            auto it = g_tune.find(tune_key(ctx->g, p, d, 0));
+            ctx->shape[p][d] = it != g_tune.end() ? it->second : def;
+            auto is = g_tune.find(tune_key(ctx->g, p, d, 1));
+            ctx->shape_schur[p][d] = is != g_tune.end() ? is->second : def;
         }
 }
 
@@ -439,7 +443,7 @@ int dwf_tune(dwf_ctx ctx, int prec, int dagger, double *best_us, void *stream) {
         release();
         return rc;
     }
-    // candidates: site kernel (workgroup sizes x XCD remap x store kind), row kernel (rows x tiles x remap)
+    // candidates: site kernel (workgroup sizes x XCD remap x store kind), row kernel (rows x tiles x remap x cap)
     std::vector<DhopShape> cand;
     for (int nt : {0, 1})
         for (int threads : {64, 128, 192, 256, 320, 384, 448, 512}) {
@@ -475,63 +479,80 @@ int dwf_tune(dwf_ctx ctx, int prec, int dagger, double *best_us, void *stream) {
     hipEvent_t e0, e1;
     DWF_HIP(hipEventCreate(&e0));
     DWF_HIP(hipEventCreate(&e1));
-    double best = 1e30;
-    DhopShape best_s = cand[0];
-    const int reps = 10;
-    bool have_ref = false;
+    const size_t rb = prec == DWF_F64 ? 8 : 4;  // bytes of the arithmetic type (M5op^-1 LDS exchange)
+    // family 0: the plain hopping launch; family 1: the fused Schur pair (M5op^-1 epilogue into a
+    // temporary, then the M5op epilogue), the shape the operators and the solvers use
+    DhopShape best_s[2] = {cand[0], cand[0]};
+    double best[2] = {1e30, 1e30};
     int status = DWF_OK;
-    for (const DhopShape &s : cand) {
-        // every shape must reproduce the first one's output bit for bit
-        DhopCall c{in, out, nullptr, 1, dagger, EPI_SCALE, 1.0, 0.0, prec, prec};
-        if ((rc = launch_dhop(ctx, c, s, st))) continue;
-        if (!have_ref) {
-            DWF_HIP(hipMemcpyAsync(ref, out, cb, hipMemcpyDeviceToDevice, st));
-            have_ref = true;
-        } else {
-            DWF_HIP(hipMemsetAsync(ndiff, 0, sizeof(unsigned), st));
-            if ((rc = launch_count_diff(out, ref, cb, ndiff, st))) {
-                status = rc;
-                break;
+    for (int family = 0; family < 2 && status == DWF_OK; ++family) {
+        auto run = [&](const DhopShape &s, int parity) -> int {
+            if (family == 0) {
+                DhopCall c{in, out, nullptr, parity, dagger, EPI_SCALE, 1.0, 0.0, prec, prec};
+                return launch_dhop(ctx, c, s, st);
             }
-            unsigned h = 0;
-            DWF_HIP(hipMemcpyAsync(&h, ndiff, sizeof(unsigned), hipMemcpyDeviceToHost, st));
-            DWF_HIP(hipStreamSynchronize(st));
-            if (h != 0) {
-                status = fail(DWF_EHIP, "dwf_tune: a launch shape changed the result (" + std::to_string(h) +
-                                            " vectors differ): rows=" + std::to_string(s.rows) +
-                                            " spb=" + std::to_string(s.spb));
-                break;
+            DhopCall c1{in, ctx->tmp[0], nullptr, 0, dagger, EPI_M5INV, 1.0, 0.0, prec, prec};
+            int r = launch_dhop(ctx, c1, s, st);
+            if (r) return r;
+            DhopCall c2{ctx->tmp[0], out, in, 1, dagger, EPI_M5, -0.25, 0.0, prec, prec};
+            return launch_dhop(ctx, c2, s, st);
+        };
+        bool have_ref = false;
+        for (const DhopShape &s : cand) {
+            if (family == 1 && s.rows == 0 && (size_t)s.spb * g.Ls * 25 * rb > ctx->lds_limit) continue;
+            // every shape must reproduce the first one's output bit for bit
+            if ((rc = run(s, 1))) continue;
+            if (!have_ref) {
+                DWF_HIP(hipMemcpyAsync(ref, out, cb, hipMemcpyDeviceToDevice, st));
+                have_ref = true;
+            } else {
+                DWF_HIP(hipMemsetAsync(ndiff, 0, sizeof(unsigned), st));
+                if ((rc = launch_count_diff(out, ref, cb, ndiff, st))) {
+                    status = rc;
+                    break;
+                }
+                unsigned h = 0;
+                DWF_HIP(hipMemcpyAsync(&h, ndiff, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+                DWF_HIP(hipStreamSynchronize(st));
+                if (h != 0) {
+                    status = fail(DWF_EHIP, "dwf_tune: a launch shape changed the result (" + std::to_string(h) +
+                                                " vectors differ): rows=" + std::to_string(s.rows) +
+                                                " spb=" + std::to_string(s.spb));
+                    break;
+                }
             }
-        }
-        DWF_HIP(hipEventRecord(e0, st));
-        for (int r = 0; r < reps; ++r) {
-            c.out_parity = r & 1;
-            launch_dhop(ctx, c, s, st);
-        }
-        DWF_HIP(hipEventRecord(e1, st));
-        DWF_HIP(hipEventSynchronize(e1));
-        float ms = 0;
-        DWF_HIP(hipEventElapsedTime(&ms, e0, e1));
-        const double us = 1000.0 * ms / reps;
-        if (std::getenv("DWF_LOG"))
-            std::fprintf(stderr,
-                         "[dwf] tune prec=%d dagger=%d nt=%d spb=%d rows=%d tile=%dx%dx%d xcd=%d occ=%d: %.2f us\n",
-                         prec, dagger, s.nt_store, s.spb, s.rows, s.ty, s.tz, s.tt, s.xcd, s.occ, us);
-        if (us < best) {
-            best = us;
-            best_s = s;
+            const int reps = 10;
+            DWF_HIP(hipEventRecord(e0, st));
+            for (int r = 0; r < reps; ++r) run(s, family == 0 ? (r & 1) : 1);
+            DWF_HIP(hipEventRecord(e1, st));
+            DWF_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            DWF_HIP(hipEventElapsedTime(&ms, e0, e1));
+            const double us = 1000.0 * ms / reps;
+            if (std::getenv("DWF_LOG"))
+                std::fprintf(stderr,
+                             "[dwf] tune %s prec=%d dagger=%d nt=%d spb=%d rows=%d tile=%dx%dx%d xcd=%d occ=%d: "
+                             "%.2f us\n",
+                             family ? "schur" : "dhop", prec, dagger, s.nt_store, s.spb, s.rows, s.ty, s.tz, s.tt,
+                             s.xcd, s.occ, us);
+            if (us < best[family]) {
+                best[family] = us;
+                best_s[family] = s;
+            }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    hipStreamSynchronize(st);
+    (void)hipStreamSynchronize(st);
     release();
     if (status != DWF_OK) return status;
-    ctx->shape[prec][dagger] = best_s;
+    ctx->shape[prec][dagger] = best_s[0];
+    ctx->shape_schur[prec][dagger] = best_s[1];
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_load_locked();
-        g_tune[tune_key(ctx->g, prec, dagger)] = best_s;
+        g_tune[tune_key(ctx->g, prec, dagger, 0)] = best_s[0];
+        g_tune[tune_key(ctx->g, prec, dagger, 1)] = best_s[1];
         if (const char *path = std::getenv("DWF_TUNE_CACHE")) {
             std::ofstream f(path, std::ios::trunc);
             for (auto &kv : g_tune)
@@ -540,7 +561,7 @@ int dwf_tune(dwf_ctx ctx, int prec, int dagger, double *best_us, void *stream) {
                   << kv.second.occ << '\n';
         }
     }
-    if (best_us) *best_us = best;
+    if (best_us) *best_us = best[0];
     return DWF_OK;
 }
 

@@ -114,7 +114,8 @@ struct dwf_ctx_s {
     double *scal = nullptr;      // device scalars of the solvers
     double *host_scal = nullptr; // pinned host mirror (16 doubles)
     void *events[2] = {};        // hipEvent_t pair for the solver's lagged stop check
-    dwf::DhopShape shape[4][2];  // tuned launch shape per (prec, dagger)
+    dwf::DhopShape shape[4][2];        // tuned launch shape per (prec, dagger): plain hopping launches
+    dwf::DhopShape shape_schur[4][2];  // the same for the fused Schur kernels (M5op, M5op^-1, CG epilogues)
     size_t lds_limit = 65536;    // LDS bytes one workgroup may allocate on this device
     size_t lds_per_cu = 65536;   // LDS bytes of one compute unit
     double inner_tol = 0.0;

@@ -59,14 +59,41 @@ __device__ __forceinline__ Off spinor_off(long row, int Ls, int s) {
     return (Off)(((Off)row * (Off)(NG * Ls) + (Off)s) * (Off)16);
 }
 
+// Spin projection of one (site, s) from its NG 16-byte vectors.  FP16 storage
+// projects straight from the packed halves (project_f16); the others unpack first.
+template <int PI, int MU, int TAU>
+__device__ __forceinline__ void project_vecs(const u32x4 *v, typename PT<PI>::A *h) {
+    if constexpr (PI == DWF_F16) {
+        unsigned w[12];
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            w[4 * g] = v[g].x;
+            w[4 * g + 1] = v[g].y;
+            w[4 * g + 2] = v[g].z;
+            w[4 * g + 3] = v[g].w;
+        }
+        project_f16<MU, TAU>(w, h);
+    } else {
+        constexpr int R2 = 2 * PT<PI>::G, NG = 12 / PT<PI>::G;
+        typename PT<PI>::A p[24];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) unpack16<PI>(v[g], p + R2 * g);
+        project<MU, TAU>(p, h);
+    }
+}
+
 template <int PI, int DIR, int MU, int TAU, typename Off>
 __device__ __forceinline__ void hop(const char *links, const char *in, int Ls, long c, long nb, int s,
                                     typename PT<PI>::A *acc) {
     using A = typename PT<PI>::A;
-    A w[18], p[24], h[12];
+    constexpr int NG = 12 / PT<PI>::G;
+    A w[18], h[12];
     load_link<PI>(links, c, DIR, w);
-    load_spinor_off<PI>(in, spinor_off<PI, Off>(nb, Ls, s), Ls * 16, p);
-    project<MU, TAU>(p, h);
+    u32x4 v[NG];
+    const Off off = spinor_off<PI, Off>(nb, Ls, s);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) v[g] = *(const u32x4 *)(in + off + (Off)(g * Ls * 16));
+    project_vecs<PI, MU, TAU>(v, h);
     mul_reconstruct<MU, TAU>(w, h, acc);
 }
 

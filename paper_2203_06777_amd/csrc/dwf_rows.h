@@ -238,18 +238,22 @@ __device__ __forceinline__ void row_block(const DhopArgs &a, unsigned q0, const 
         constexpr int SG = DAG ? 1 : -1;
 #define DWF_HOP_LDS(DIR, MU, TAU, LX)                                                        \
     {                                                                                        \
-        A w[18], p[24], h[12];                                                               \
+        A w[18], h[12];                                                                      \
+        u32x4 v[NG];                                                                         \
         load_link<PI>(lk, 0, DIR, w);                                                        \
-        _Pragma("unroll") for (int g = 0; g < NG; ++g) unpack16<PI>(xr[((LX)*NG + g) * Ls + s], p + R2 * g); \
-        project<MU, TAU>(p, h);                                                              \
+        _Pragma("unroll") for (int g = 0; g < NG; ++g) v[g] = xr[((LX)*NG + g) * Ls + s];    \
+        project_vecs<PI, MU, TAU>(v, h);                                                     \
         mul_reconstruct<MU, TAU>(w, h, acc);                                                 \
     }
 #define DWF_HOP_GLB(DIR, MU, TAU, NB)                                                        \
     {                                                                                        \
-        A w[18], p[24], h[12];                                                               \
+        A w[18], h[12];                                                                      \
+        u32x4 v[NG];                                                                         \
         load_link<PI>(lk, 0, DIR, w);                                                        \
-        load_spinor_off<PI>(in_f, spinor_off<PI, Off>(NB, Ls, s), Ls * 16, p);               \
-        project<MU, TAU>(p, h);                                                              \
+        const Off off_ = spinor_off<PI, Off>(NB, Ls, s);                                     \
+        _Pragma("unroll") for (int g = 0; g < NG; ++g) v[g] =                                \
+            *(const u32x4 *)(in_f + off_ + (Off)(g * Ls * 16));                              \
+        project_vecs<PI, MU, TAU>(v, h);                                                     \
         mul_reconstruct<MU, TAU>(w, h, acc);                                                 \
     }
         DWF_HOP_LDS(0, 0, SG, lx0)

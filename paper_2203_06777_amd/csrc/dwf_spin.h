@@ -40,6 +40,61 @@ __device__ __forceinline__ void project(const A *__restrict__ p, A *__restrict__
     }
 }
 
+// FP16 storage: one half-spinor component u + S * l straight from the packed
+// words (complex = re in the low half, im in the high half), as one v_fma_mix_f32
+// (f16 operands, f32 result, one rounding).  Bit for bit the FP32 sum of the
+// converted halves, without the two conversions.  LH / UH select the high half.
+template <int LH, int UH, int S>
+__device__ __forceinline__ float mix_add(unsigned l, unsigned u) {
+    float r;
+#define DWF_MIX(LS, US, C) \
+    asm("v_fma_mix_f32 %0, %1, " C ", %2 op_sel:[" #LS ",0," #US "] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(l), "v"(u))
+    if constexpr (S > 0) {
+        if constexpr (LH == 0 && UH == 0) DWF_MIX(0, 0, "1.0");
+        else if constexpr (LH == 0 && UH == 1) DWF_MIX(0, 1, "1.0");
+        else if constexpr (LH == 1 && UH == 0) DWF_MIX(1, 0, "1.0");
+        else DWF_MIX(1, 1, "1.0");
+    } else {
+        if constexpr (LH == 0 && UH == 0) DWF_MIX(0, 0, "-1.0");
+        else if constexpr (LH == 0 && UH == 1) DWF_MIX(0, 1, "-1.0");
+        else if constexpr (LH == 1 && UH == 0) DWF_MIX(1, 0, "-1.0");
+        else DWF_MIX(1, 1, "-1.0");
+    }
+#undef DWF_MIX
+    return r;
+}
+
+// project<MU, TAU> for FP16 storage from the 12 packed words of a spinor
+// (word k = spin * 3 + colour); same identities as project.
+template <int MU, int TAU>
+__device__ __forceinline__ void project_f16(const unsigned *__restrict__ w, float *__restrict__ h) {
+#pragma unroll
+    for (int col = 0; col < 3; ++col) {
+        const unsigned u0 = w[col], u1 = w[3 + col], l0 = w[6 + col], l1 = w[9 + col];
+        if constexpr (MU == 0) {  // e l = (-i l1, -i l0)
+            h[2 * col] = mix_add<1, 0, TAU>(l1, u0);
+            h[2 * col + 1] = mix_add<0, 1, -TAU>(l1, u0);
+            h[2 * (3 + col)] = mix_add<1, 0, TAU>(l0, u1);
+            h[2 * (3 + col) + 1] = mix_add<0, 1, -TAU>(l0, u1);
+        } else if constexpr (MU == 1) {  // (-l1, l0)
+            h[2 * col] = mix_add<0, 0, -TAU>(l1, u0);
+            h[2 * col + 1] = mix_add<1, 1, -TAU>(l1, u0);
+            h[2 * (3 + col)] = mix_add<0, 0, TAU>(l0, u1);
+            h[2 * (3 + col) + 1] = mix_add<1, 1, TAU>(l0, u1);
+        } else if constexpr (MU == 2) {  // (-i l0, i l1)
+            h[2 * col] = mix_add<1, 0, TAU>(l0, u0);
+            h[2 * col + 1] = mix_add<0, 1, -TAU>(l0, u0);
+            h[2 * (3 + col)] = mix_add<1, 0, -TAU>(l1, u1);
+            h[2 * (3 + col) + 1] = mix_add<0, 1, TAU>(l1, u1);
+        } else {  // (l0, l1)
+            h[2 * col] = mix_add<0, 0, TAU>(l0, u0);
+            h[2 * col + 1] = mix_add<1, 1, TAU>(l0, u0);
+            h[2 * (3 + col)] = mix_add<0, 0, TAU>(l1, u1);
+            h[2 * (3 + col) + 1] = mix_add<1, 1, TAU>(l1, u1);
+        }
+    }
+}
+
 // acc += (chi, TAU * e_MU^dag chi) for chi = W h (both spin components).
 template <int MU, int TAU, typename A>
 __device__ __forceinline__ void mul_reconstruct(const A *__restrict__ w, const A *__restrict__ h,

@@ -10,7 +10,7 @@ namespace dwf {
 
 static int two_step(dwf_ctx ctx, void *out, int prec_out, const void *in, void *t_e, int dagger, int prec,
                     hipStream_t st, double *norm_out = nullptr, long *nparts = nullptr) {
-    const DhopShape &sh = ctx->shape[prec][dagger];
+    const DhopShape &sh = ctx->shape_schur[prec][dagger];
     DhopCall c1{in, t_e, nullptr, 0, dagger, EPI_M5INV, 1.0, 0.0, prec, prec};
     int rc = launch_dhop(ctx, c1, sh, st);
     if (rc) return rc;
@@ -36,7 +36,7 @@ int op_mdagm(dwf_ctx ctx, void *out, const void *in, int prec, void *tmp_o, hipS
 // r -= alpha M_pc^dag y to r (prec_r) and writes partials of the new |r|^2.
 int op_mpcdag_cg(dwf_ctx ctx, void *r, int prec_r, const void *y, int prec, const double *cg_alpha,
                  const double *cg_live, double *partials, long *nparts, hipStream_t st) {
-    const DhopShape &sh = ctx->shape[prec][1];
+    const DhopShape &sh = ctx->shape_schur[prec][1];
     DhopCall c1{y, ctx->tmp[0], nullptr, 0, 1, EPI_M5INV, 1.0, 0.0, prec, prec};
     int rc = launch_dhop(ctx, c1, sh, st);
     if (rc) return rc;
