@@ -150,8 +150,7 @@ int dwf_cg(dwf_ctx ctx, void *x, const void *b, double tol, int maxit, int mode,
            void *stream);
 
 /* Inner-solve controls of modes 1-3: relative residual target of each inner
- * solve and its iteration cap (<= 0 restores the defaults 1e-5 / 1e-3 for
- * FP32 / 16-bit and 2000). */
+ * solve and its iteration cap (<= 0 restores the defaults 1e-2 and 2000). */
 int dwf_cg_set_inner(dwf_ctx ctx, double inner_tol, int inner_maxit);
 
 /* Solves D_DW x = b (dagger = 0) or D_DW^dag x = b (dagger = 1) on full FP64
