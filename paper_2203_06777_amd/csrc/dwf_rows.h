@@ -205,27 +205,75 @@ __device__ __forceinline__ void row_block(const DhopArgs &a, unsigned q0, const 
     constexpr int kL = PI == DWF_F64 ? 5 : (PI == DWF_F32 ? 3 : 2);
     constexpr int kX = PI == DWF_F64 ? 12 : (PI == DWF_F32 ? 6 : 3);
     const int nrow_here = (int)min((unsigned)a.rows, a.nrows - q0);
-    for (int rr = 0; rr < nrow_here && t < nthr; ++rr) {
-        unsigned y1, y2, y3;  // uniform across the workgroup
-        rowmap(a, q0 + rr, y1, y2, y3);
-        const size_t prow = y1 + a.lat.L1 * (y2 + a.lat.L2 * y3);
-        const u32x4 *gl = (const u32x4 *)links_g + prow * VL;
-        const u32x4 *gx = (const u32x4 *)in_f + prow * VX;
-        u32x4 *dl = lds_l + rr * VL;
-        u32x4 *dx = lds_x + rr * VX;
-        u32x4 bl[kL], bx[kX];
+    // FP16 storage: the six global neighbours of the lane (18 vectors) are requested together with
+    // the staging loads, so a workgroup's reads of each neighbour row fall close together in time
+    // and the rows neighbouring workgroups share are still in L2 (measured: ~10% less fetch and
+    // 5-7% less time; at FP32 and BF16 the extra registers cost more occupancy than that gains).
+    constexpr bool kPrefetch = PI == DWF_F16;
+    u32x4 nbv[kPrefetch ? 6 : 1][NG];
+    if constexpr (kPrefetch) {
+        const bool stager = t < nthr;
+        {  // first row of the block: its staging loads, the neighbour loads, then the LDS writes
+            unsigned y1, y2, y3;  // uniform across the workgroup
+            rowmap(a, q0, y1, y2, y3);
+            const size_t prow = y1 + a.lat.L1 * (y2 + a.lat.L2 * y3);
+            const u32x4 *gl = (const u32x4 *)links_g + prow * VL;
+            const u32x4 *gx = (const u32x4 *)in_f + prow * VX;
+            u32x4 bl[kL], bx[kX];
 #pragma unroll
-        for (int u = 0; u < kL; ++u) bl[u] = gl[min(t + u * nthr, VL - 1)];
+            for (int u = 0; u < kL; ++u) bl[u] = gl[min(t + u * nthr, VL - 1)];
 #pragma unroll
-        for (int u = 0; u < kX; ++u) bx[u] = gx[min(t + u * nthr, VX - 1)];
+            for (int u = 0; u < kX; ++u) bx[u] = gx[min(t + u * nthr, VX - 1)];
+            const Off nbs[6] = {nb1, nb2, nb3, nb5, nb6, nb7};  // in bounds for idle lanes too (row 0)
 #pragma unroll
-        for (int u = 0; u < kL; ++u)
-            if (t + u * nthr < VL) dl[t + u * nthr] = bl[u];
+            for (int k = 0; k < 6; ++k) {
+                const Off off = spinor_off<PI, Off>(nbs[k], Ls, s);
 #pragma unroll
-        for (int u = 0; u < kX; ++u)
-            if (t + u * nthr < VX) dx[t + u * nthr] = bx[u];
-        for (int v = t + kL * nthr; v < VL; v += nthr) dl[v] = gl[v];
-        for (int v = t + kX * nthr; v < VX; v += nthr) dx[v] = gx[v];
+                for (int g = 0; g < NG; ++g) nbv[k][g] = *(const u32x4 *)(in_f + off + (Off)(g * Ls * 16));
+            }
+#pragma unroll
+            for (int u = 0; u < kL; ++u)
+                if (stager && t + u * nthr < VL) lds_l[t + u * nthr] = bl[u];
+#pragma unroll
+            for (int u = 0; u < kX; ++u)
+                if (stager && t + u * nthr < VX) lds_x[t + u * nthr] = bx[u];
+            if (stager) {
+                for (int v = t + kL * nthr; v < VL; v += nthr) lds_l[v] = gl[v];
+                for (int v = t + kX * nthr; v < VX; v += nthr) lds_x[v] = gx[v];
+            }
+        }
+        for (int rr = 1; rr < nrow_here && stager; ++rr) {
+            unsigned y1, y2, y3;
+            rowmap(a, q0 + rr, y1, y2, y3);
+            const size_t prow = y1 + a.lat.L1 * (y2 + a.lat.L2 * y3);
+            const u32x4 *gl = (const u32x4 *)links_g + prow * VL;
+            const u32x4 *gx = (const u32x4 *)in_f + prow * VX;
+            for (int v = t; v < VL; v += nthr) lds_l[rr * VL + v] = gl[v];
+            for (int v = t; v < VX; v += nthr) lds_x[rr * VX + v] = gx[v];
+        }
+    } else {
+        for (int rr = 0; rr < nrow_here && t < nthr; ++rr) {
+            unsigned y1, y2, y3;  // uniform across the workgroup
+            rowmap(a, q0 + rr, y1, y2, y3);
+            const size_t prow = y1 + a.lat.L1 * (y2 + a.lat.L2 * y3);
+            const u32x4 *gl = (const u32x4 *)links_g + prow * VL;
+            const u32x4 *gx = (const u32x4 *)in_f + prow * VX;
+            u32x4 *dl = lds_l + rr * VL;
+            u32x4 *dx = lds_x + rr * VX;
+            u32x4 bl[kL], bx[kX];
+#pragma unroll
+            for (int u = 0; u < kL; ++u) bl[u] = gl[min(t + u * nthr, VL - 1)];
+#pragma unroll
+            for (int u = 0; u < kX; ++u) bx[u] = gx[min(t + u * nthr, VX - 1)];
+#pragma unroll
+            for (int u = 0; u < kL; ++u)
+                if (t + u * nthr < VL) dl[t + u * nthr] = bl[u];
+#pragma unroll
+            for (int u = 0; u < kX; ++u)
+                if (t + u * nthr < VX) dx[t + u * nthr] = bx[u];
+            for (int v = t + kL * nthr; v < VL; v += nthr) dl[v] = gl[v];
+            for (int v = t + kX * nthr; v < VX; v += nthr) dx[v] = gx[v];
+        }
     }
     __syncthreads();
 
@@ -256,14 +304,33 @@ __device__ __forceinline__ void row_block(const DhopArgs &a, unsigned q0, const 
         project_vecs<PI, MU, TAU>(v, h);                                                     \
         mul_reconstruct<MU, TAU>(w, h, acc);                                                 \
     }
-        DWF_HOP_LDS(0, 0, SG, lx0)
-        DWF_HOP_GLB(1, 1, SG, nb1)
-        DWF_HOP_GLB(2, 2, SG, nb2)
-        DWF_HOP_GLB(3, 3, SG, nb3)
-        DWF_HOP_LDS(4, 0, -SG, lx4)
-        DWF_HOP_GLB(5, 1, -SG, nb5)
-        DWF_HOP_GLB(6, 2, -SG, nb6)
-        DWF_HOP_GLB(7, 3, -SG, nb7)
+#define DWF_HOP_REG(DIR, MU, TAU, K)                                                         \
+    {                                                                                        \
+        A w[18], h[12];                                                                      \
+        load_link<PI>(lk, 0, DIR, w);                                                        \
+        project_vecs<PI, MU, TAU>(nbv[K], h);                                                \
+        mul_reconstruct<MU, TAU>(w, h, acc);                                                 \
+    }
+        if constexpr (kPrefetch) {
+            DWF_HOP_LDS(0, 0, SG, lx0)
+            DWF_HOP_REG(1, 1, SG, 0)
+            DWF_HOP_REG(2, 2, SG, 1)
+            DWF_HOP_REG(3, 3, SG, 2)
+            DWF_HOP_LDS(4, 0, -SG, lx4)
+            DWF_HOP_REG(5, 1, -SG, 3)
+            DWF_HOP_REG(6, 2, -SG, 4)
+            DWF_HOP_REG(7, 3, -SG, 5)
+        } else {
+            DWF_HOP_LDS(0, 0, SG, lx0)
+            DWF_HOP_GLB(1, 1, SG, nb1)
+            DWF_HOP_GLB(2, 2, SG, nb2)
+            DWF_HOP_GLB(3, 3, SG, nb3)
+            DWF_HOP_LDS(4, 0, -SG, lx4)
+            DWF_HOP_GLB(5, 1, -SG, nb5)
+            DWF_HOP_GLB(6, 2, -SG, nb6)
+            DWF_HOP_GLB(7, 3, -SG, nb7)
+        }
+#undef DWF_HOP_REG
 #undef DWF_HOP_LDS
 #undef DWF_HOP_GLB
     }
