@@ -8,18 +8,16 @@
 // where P^-+ takes the two-spin projection u -+ e_mu l of (1 -+ gamma_mu).
 // kind 0 writes eta (M^dag + N), the Euclidean gradient; kind 1 writes the
 // traceless Hermitian part of (i/2)(G - G^dag), G = eta (U M - N U^dag).
-// One lane per (site, mu); a bandwidth pass over X, Y and the links.
+#include <algorithm>
+
 #include "dwf_device.h"
 #include "dwf_spin.h"
 
 namespace dwf {
 
-template <int MU>
-__device__ inline void accum_outer(const double *xa, const double *ya, const double *xb, const double *yb, double *m,
-                                   double *n) {
-    double h[12], g[12];
-    project<MU, -1>(xa, h);
-    project<MU, -1>(ya, g);
+// acc_{ba} += sum_k h_k(b) conj(g_k(a)) with h, g the two-spin projections
+// (two colour vectors each, re/im interleaved).
+__device__ inline void accum_outer(const double *h, const double *g, double *acc) {
 #pragma unroll
     for (int b = 0; b < 3; ++b)
 #pragma unroll
@@ -28,144 +26,207 @@ __device__ inline void accum_outer(const double *xa, const double *ya, const dou
             for (int k = 0; k < 2; ++k) {
                 const double hr = h[2 * (3 * k + b)], hi = h[2 * (3 * k + b) + 1];
                 const double gr = g[2 * (3 * k + a)], gi = g[2 * (3 * k + a) + 1];
-                m[2 * (3 * b + a)] += hr * gr + hi * gi;
-                m[2 * (3 * b + a) + 1] += hi * gr - hr * gi;
-            }
-    project<MU, 1>(xb, h);
-    project<MU, 1>(yb, g);
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const double hr = h[2 * (3 * k + b)], hi = h[2 * (3 * k + b) + 1];
-                const double gr = g[2 * (3 * k + a)], gi = g[2 * (3 * k + a) + 1];
-                n[2 * (3 * b + a)] += hr * gr + hi * gi;
-                n[2 * (3 * b + a) + 1] += hi * gr - hr * gi;
+                acc[2 * (3 * b + a)] += hr * gr + hi * gi;
+                acc[2 * (3 * b + a) + 1] += hi * gr - hr * gi;
             }
 }
 
-// c = a * b for 3x3 complex (row-major, re/im interleaved); bdag: use b^dag.
-__device__ inline void mat_mul(const double *a, const double *b, double *c, bool adag, bool bdag) {
+// h = u + tau e_MU l with tau = +-1 held in a register (same values as the
+// compile-time projection: tau * e is exact, so the fma rounds once).
+template <int MU>
+__device__ inline void project_tau(const double *p, double tau, double *h) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            double re = 0, im = 0;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const int ia = adag ? (3 * k + i) : (3 * i + k);
-                const int ib = bdag ? (3 * j + k) : (3 * k + j);
-                const double ar = a[2 * ia], ai = adag ? -a[2 * ia + 1] : a[2 * ia + 1];
-                const double br = b[2 * ib], bi = bdag ? -b[2 * ib + 1] : b[2 * ib + 1];
-                re += ar * br - ai * bi;
-                im += ar * bi + ai * br;
-            }
-            c[2 * (3 * i + j)] = re;
-            c[2 * (3 * i + j) + 1] = im;
+    for (int col = 0; col < 3; ++col) {
+        const double u0r = p[2 * col], u0i = p[2 * col + 1];
+        const double u1r = p[2 * (3 + col)], u1i = p[2 * (3 + col) + 1];
+        const double l0r = p[2 * (6 + col)], l0i = p[2 * (6 + col) + 1];
+        const double l1r = p[2 * (9 + col)], l1i = p[2 * (9 + col) + 1];
+        double e0r, e0i, e1r, e1i;
+        if constexpr (MU == 0) {  // e l = (-i l1, -i l0)
+            e0r = l1i; e0i = -l1r; e1r = l0i; e1i = -l0r;
+        } else if constexpr (MU == 1) {  // (-l1, l0)
+            e0r = -l1r; e0i = -l1i; e1r = l0r; e1i = l0i;
+        } else if constexpr (MU == 2) {  // (-i l0, i l1)
+            e0r = l0i; e0i = -l0r; e1r = -l1i; e1i = l1r;
+        } else {  // (l0, l1)
+            e0r = l0r; e0i = l0i; e1r = l1r; e1i = l1i;
         }
+        h[2 * col] = fma_(tau, e0r, u0r);
+        h[2 * col + 1] = fma_(tau, e0i, u0i);
+        h[2 * (3 + col)] = fma_(tau, e1r, u1r);
+        h[2 * (3 + col) + 1] = fma_(tau, e1i, u1i);
+    }
+}
+
+// G_ab = (W M)_ab - (N W^dag)_ab for 3x3 complex matrices (row-major, re/im
+// interleaved); w in global memory, m and n in LDS.
+__device__ inline void g_entry(const double *w, const double *m, const double *n, int a, int b, double &re,
+                               double &im) {
+    re = 0;
+    im = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double wr = w[2 * (3 * a + k)], wi = w[2 * (3 * a + k) + 1];
+        const double mr = m[2 * (3 * k + b)], mi = m[2 * (3 * k + b) + 1];
+        re += wr * mr - wi * mi;
+        im += wr * mi + wi * mr;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double nr = n[2 * (3 * a + k)], ni = n[2 * (3 * a + k) + 1];
+        const double vr = w[2 * (3 * b + k)], vi = -w[2 * (3 * b + k) + 1];
+        re -= nr * vr - ni * vi;
+        im -= nr * vi + ni * vr;
+    }
 }
 
 struct ForceArgs {
     double *F;
     const u32x4 *X, *Y;
     const double *links[2];  // FP64 gathered links per parity (eta U in dir mu)
-    long vol, cbv;           // 4D volume; 16-byte vectors per checkerboard field
-    int L0, L1, L2, L3, Ls, kind, antiperiodic;
+    long cbv;                // 16-byte vectors per checkerboard field
+    unsigned vol, L0, L1, L2, L3;
+    unsigned ty, tz;         // (y, z) tile of the visiting order
+    unsigned ns, nblk;       // sites per workgroup, workgroups
+    int Ls, kind, antiperiodic;
     double scale;
 };
 
-__global__ void __launch_bounds__(256) k_force(const ForceArgs a) {
-    const long t = (long)blockIdx.x * 256 + threadIdx.x;
-    if (t >= a.vol * 4) return;
-    const long i = t >> 2;
-    const int mu = (int)(t & 3);
-    int x[4];
-    x[0] = (int)(i % a.L0);
-    long r = i / a.L0;
-    x[1] = (int)(r % a.L1);
-    r /= a.L1;
-    x[2] = (int)(r % a.L2);
-    x[3] = (int)(r / a.L2);
-    const int par = (x[0] + x[1] + x[2] + x[3]) & 1;
-    const int L[4] = {a.L0, a.L1, a.L2, a.L3};
-    int y[4] = {x[0], x[1], x[2], x[3]};
-    y[mu] = (x[mu] + 1) % L[mu];
-    const long cx = i >> 1;
-    const long cy = (y[0] + (long)a.L0 * (y[1] + (long)a.L1 * (y[2] + (long)a.L2 * y[3]))) >> 1;
-    const u32x4 *Xx = a.X + par * a.cbv, *Xy = a.X + (1 - par) * a.cbv;
-    const u32x4 *Yx = a.Y + par * a.cbv, *Yy = a.Y + (1 - par) * a.cbv;
-    double m[18], n[18];
+// Visiting order of the sites: x fastest, then t, then y and z inside a
+// ty x tz tile, then the tiles.  Returns the lexicographic index of the o-th
+// site and its coordinates.  A site is then read as the +t neighbour L0 sites
+// before it is read as own data, as the +y neighbour L0 Lt sites before and as
+// the +z neighbour L0 Lt ty sites before, so those re-reads hit L2.
+__device__ inline unsigned visit_site(const ForceArgs &a, unsigned o, unsigned *x) {
+    x[0] = o % a.L0;
+    unsigned q = o / a.L0;
+    x[3] = q % a.L3;
+    q /= a.L3;
+    const unsigned ly = q % a.ty;
+    q /= a.ty;
+    const unsigned lz = q % a.tz;
+    q /= a.tz;
+    const unsigned nty = a.L1 / a.ty;
+    x[1] = (q % nty) * a.ty + ly;
+    x[2] = (q / nty) * a.tz + lz;
+    return x[0] + a.L0 * (x[1] + a.L1 * (x[2] + a.L2 * x[3]));
+}
+
+// A workgroup takes ns consecutive sites of the visiting order and all their
+// links; each XCD takes one contiguous part of the workgroups.  Lane
+// ((mu * 2 + term) * ns + site) * Ls + s computes the slice-s outer product of
+// one term: term 0 builds M from P^- X(x+mu) and P^- Y(x), term 1 builds N from
+// P^+ X(x) and P^+ Y(x+mu).  The Ls lanes of a (mu, term, site) are adjacent,
+// so every spinor read is Ls consecutive 16-byte vectors, and mu is uniform
+// over a wavefront whenever 2 ns Ls is a multiple of 64.  The products are
+// summed over s in LDS in a fixed order (bitwise reproducible); then nine
+// lanes per link form the nine colour entries of the force.
+constexpr int kForceMaxThreads = 512;
+
+__global__ void __launch_bounds__(kForceMaxThreads) k_force(const ForceArgs a) {
+    extern __shared__ double red[];  // [mu][term][site][s][18]
+    const unsigned nxcd = 8, per = (a.nblk + nxcd - 1) / nxcd;
+    const unsigned lb = (blockIdx.x % nxcd) * per + blockIdx.x / nxcd;
+    if (lb >= a.nblk) return;  // whole workgroup
+    const int Ls = a.Ls;
+    const unsigned ns = a.ns;
+    const int t = threadIdx.x;
+    const unsigned grp = (unsigned)t / (unsigned)Ls;
+    const int s = t - (int)grp * Ls;
+    const unsigned sl = grp % ns, mt = grp / ns;
+    const int mu = (int)(mt >> 1), term = (int)(mt & 1);
+    const unsigned o = lb * ns + sl;
+    double acc[18];
 #pragma unroll
-    for (int k = 0; k < 18; ++k) m[k] = n[k] = 0;
-    for (int s = 0; s < a.Ls; ++s) {
-        double xa[24], ya[24], xb[24], yb[24];
-        load_spinor<DWF_F64>(Xy, cy, a.Ls, s, xa);  // X(x+mu)
-        load_spinor<DWF_F64>(Yx, cx, a.Ls, s, ya);  // Y(x)
-        load_spinor<DWF_F64>(Xx, cx, a.Ls, s, xb);  // X(x)
-        load_spinor<DWF_F64>(Yy, cy, a.Ls, s, yb);  // Y(x+mu)
+    for (int k = 0; k < 18; ++k) acc[k] = 0;
+    if (o < a.vol) {
+        unsigned x[4];
+        const unsigned i = visit_site(a, o, x);
+        const int par = (int)((x[0] + x[1] + x[2] + x[3]) & 1);
+        const unsigned xm = mu == 0 ? x[0] : (mu == 1 ? x[1] : (mu == 2 ? x[2] : x[3]));
+        const unsigned Lm = mu == 0 ? a.L0 : (mu == 1 ? a.L1 : (mu == 2 ? a.L2 : a.L3));
+        const unsigned st = mu == 0 ? 1u : (mu == 1 ? a.L0 : (mu == 2 ? a.L0 * a.L1 : a.L0 * a.L1 * a.L2));
+        const unsigned iy = xm + 1 == Lm ? i - (Lm - 1) * st : i + st;  // x + mu
+        const long cx = i >> 1, cy = iy >> 1;
+        const u32x4 *xs = term ? a.X + par * a.cbv : a.X + (1 - par) * a.cbv;
+        const u32x4 *ys = term ? a.Y + (1 - par) * a.cbv : a.Y + par * a.cbv;
+        double xv[24], yv[24], h[12], g[12];
+        load_spinor<DWF_F64>(xs, term ? cx : cy, Ls, s, xv);
+        load_spinor<DWF_F64>(ys, term ? cy : cx, Ls, s, yv);
+        const double tau = term ? 1.0 : -1.0;
         switch (mu) {
-            case 0: accum_outer<0>(xa, ya, xb, yb, m, n); break;
-            case 1: accum_outer<1>(xa, ya, xb, yb, m, n); break;
-            case 2: accum_outer<2>(xa, ya, xb, yb, m, n); break;
-            default: accum_outer<3>(xa, ya, xb, yb, m, n); break;
+            case 0: project_tau<0>(xv, tau, h); project_tau<0>(yv, tau, g); break;
+            case 1: project_tau<1>(xv, tau, h); project_tau<1>(yv, tau, g); break;
+            case 2: project_tau<2>(xv, tau, h); project_tau<2>(yv, tau, g); break;
+            default: project_tau<3>(xv, tau, h); project_tau<3>(yv, tau, g); break;
         }
+        accum_outer(h, g, acc);
     }
-    double out[18];
-    if (a.kind == 0) {
-        const double eta = (a.antiperiodic && mu == 3 && x[3] == a.L3 - 1) ? -1.0 : 1.0;
+    double *mine = red + (long)t * 18;
 #pragma unroll
-        for (int p = 0; p < 3; ++p)
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                out[2 * (3 * p + q)] = eta * (m[2 * (3 * q + p)] + n[2 * (3 * p + q)]);
-                out[2 * (3 * p + q) + 1] = eta * (-m[2 * (3 * q + p) + 1] + n[2 * (3 * p + q) + 1]);
-            }
-    } else {
-        const double *w = a.links[par] + (cx * 8 + mu) * 18;  // eta_mu(x) U_mu(x)
-        double wl[18], g1[18], g2[18];
-#pragma unroll
-        for (int k = 0; k < 18; ++k) wl[k] = w[k];
-        mat_mul(wl, m, g1, false, false);  // W M
-        mat_mul(n, wl, g2, false, true);   // N W^dag
-        double g[18];
-#pragma unroll
-        for (int k = 0; k < 18; ++k) g[k] = g1[k] - g2[k];
-        // K = (i/2)(G - G^dag): K_pq = (i/2)(G_pq - conj(G_qp))
-#pragma unroll
-        for (int p = 0; p < 3; ++p)
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                const double dr = g[2 * (3 * p + q)] - g[2 * (3 * q + p)];
-                const double di = g[2 * (3 * p + q) + 1] + g[2 * (3 * q + p) + 1];
-                out[2 * (3 * p + q)] = -0.5 * di;
-                out[2 * (3 * p + q) + 1] = 0.5 * dr;
-            }
-        const double tr = (out[0] + out[8] + out[16]) / 3.0;  // real part of the trace / 3
-        const double tri = (out[1] + out[9] + out[17]) / 3.0;
-        out[0] -= tr;
-        out[8] -= tr;
-        out[16] -= tr;
-        out[1] -= tri;
-        out[9] -= tri;
-        out[17] -= tri;
+    for (int k = 0; k < 18; ++k) mine[k] = acc[k];
+    __syncthreads();
+    // Lane s of a group sums components s, s + Ls, ... over the Ls slices into
+    // the group's slot 0; each component has exactly one such lane.
+    double *gp = red + (long)grp * Ls * 18;
+    for (int k = s; k < 18; k += Ls) {
+        double sum = 0;
+        for (int q = 0; q < Ls; ++q) sum += gp[q * 18 + k];
+        gp[k] = sum;
     }
-    double *f = a.F + t * 18;
+    __syncthreads();
+    for (unsigned task = t; task < ns * 36; task += blockDim.x) {
+        const unsigned jl = task / 9;  // local link: site * 4 + mu
+        const int e = (int)(task - jl * 9), p = e / 3, q = e - 3 * (e / 3);
+        const unsigned esl = jl >> 2;
+        const int emu = (int)(jl & 3);
+        const unsigned eo = lb * ns + esl;
+        if (eo >= a.vol) continue;
+        const double *m = red + (long)((emu * 2) * ns + esl) * Ls * 18;
+        const double *n = red + (long)((emu * 2 + 1) * ns + esl) * Ls * 18;
+        unsigned x[4];
+        const unsigned ei = visit_site(a, eo, x);
+        double ore, oim;
+        if (a.kind == 0) {  // eta (M^dag + N)
+            const double eta = (a.antiperiodic && emu == 3 && x[3] == a.L3 - 1) ? -1.0 : 1.0;
+            ore = eta * (m[2 * (3 * q + p)] + n[2 * (3 * p + q)]);
+            oim = eta * (-m[2 * (3 * q + p) + 1] + n[2 * (3 * p + q) + 1]);
+        } else {  // traceless part of (i/2)(G - G^dag), G = W M - N W^dag, W = eta U
+            const int par = (int)((x[0] + x[1] + x[2] + x[3]) & 1);
+            const double *w = a.links[par] + ((long)(ei >> 1) * 8 + emu) * 18;
+            double gpr, gpi, gqr, gqi;
+            g_entry(w, m, n, p, q, gpr, gpi);
+            g_entry(w, m, n, q, p, gqr, gqi);
+            ore = -0.5 * (gpi + gqi);
+            oim = 0.5 * (gpr - gqr);
+            if (p == q) {
+                double tr = 0;
 #pragma unroll
-    for (int k = 0; k < 18; ++k) f[k] = a.scale * out[k];
+                for (int r = 0; r < 3; ++r) {
+                    double grr, gri;
+                    g_entry(w, m, n, r, r, grr, gri);
+                    tr += -0.5 * (gri + gri);
+                }
+                ore -= tr / 3.0;
+            }
+        }
+        double *f = a.F + ((long)ei * 4 + emu) * 18 + 2 * e;
+        f[0] = a.scale * ore;
+        f[1] = a.scale * oim;
+    }
 }
 
 int launch_force(dwf_ctx ctx, double *F, const void *X, const void *Y, int kind, double scale, hipStream_t st) {
     const Geom &g = ctx->g;
+    if (g.vol * 4 > 0xffffffffL) return fail(DWF_EINVAL, "dwf_force: more than 2^32 links");
     ForceArgs a;
     a.F = F;
     a.X = (const u32x4 *)X;
     a.Y = (const u32x4 *)Y;
     a.links[0] = (const double *)ctx->links[DWF_F64][0];
     a.links[1] = (const double *)ctx->links[DWF_F64][1];
-    a.vol = g.vol;
     a.cbv = (long)(cb_bytes(g, DWF_F64) / 16);
+    a.vol = (unsigned)g.vol;
     a.L0 = g.L[0];
     a.L1 = g.L[1];
     a.L2 = g.L[2];
@@ -174,8 +235,21 @@ int launch_force(dwf_ctx ctx, double *F, const void *X, const void *Y, int kind,
     a.kind = kind;
     a.antiperiodic = g.antiperiodic;
     a.scale = scale;
-    const unsigned nb = (unsigned)((g.vol * 4 + 255) / 256);
-    hipLaunchKernelGGL(k_force, nb, 256, 0, st, a);
+    // y tile: the +z re-read distance L0 Lt ty sites of X and Y within ~2 MB
+    const long site_bytes = 2L * 24 * 8 * g.Ls;
+    a.ty = 1;
+    for (int t : {8, 4, 2})
+        if (g.L[1] % t == 0 && (long)g.L[0] * g.L[3] * t * site_bytes <= (2L << 20)) {
+            a.ty = t;
+            break;
+        }
+    a.tz = g.L[2] % 4 == 0 ? 4 : (g.L[2] % 2 == 0 ? 2 : 1);
+    a.ns = (unsigned)std::max(1, 256 / (8 * g.Ls));  // 8 Ls lanes per site (<= 512 for Ls <= 64)
+    a.nblk = (a.vol + a.ns - 1) / a.ns;
+    const unsigned threads = a.ns * 8 * g.Ls;
+    const unsigned grid = (a.nblk + 7) / 8 * 8;
+    const size_t shm = (size_t)threads * 18 * sizeof(double);
+    hipLaunchKernelGGL(k_force, grid, threads, shm, st, a);
     DWF_HIP(hipGetLastError());
     return DWF_OK;
 }

@@ -29,7 +29,7 @@ def D():
 # Force kernel
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("kind", [0, 1])
-@pytest.mark.parametrize("dims,ls", [((4, 4, 4, 4), 4), ((2, 4, 2, 6), 3)])
+@pytest.mark.parametrize("dims,ls", [((4, 4, 4, 4), 4), ((2, 4, 2, 6), 3), ((2, 2, 4, 2), 64)])
 def test_force_kernel(kind, dims, ls):
     op, u = make(dims, ls, seed_u=51)
     x = F.fermion_full(dims, ls, 52)
