@@ -19,6 +19,13 @@ module writes out the standard definitions with these fixed conventions:
   psi~(Ls) = -mf psi(0), psi~(-1) = -mf psi(Ls-1), P_+- = (1 +- gamma_5)/2.
 * full operator D_DW = M5op - D_h/2; Schur complement on the odd checkerboard
   M_pc = M5op - (1/4) D_h^{o<-e} M5op^-1 D_h^{e<-o}.
+* Moebius (Cayley) generalisation with real b, c (Brower, Neff and Orginos;
+  the paper does not treat it): with the fifth-dimension hop
+  (K psi)(s) = P_- psi~(s+1) + P_+ psi~(s-1) and D_W = D_W(-M5),
+  D_mob psi(s) = (b D_W + 1) psi(s) + (c D_W - 1) (K psi)(s),
+  i.e. D_mob = D_W (b + c K) + 1 - K.  b = 1, c = 0 is Shamir.  Its site-local
+  part is Mooee = [b (4-M5) + 1] - [1 - c (4-M5)] K and its hopping part
+  -D_h (b + c K) / 2, so M_pc = Mooee - (1/4) D_h^{o<-e} (b + cK) Mooee^-1 D_h^{e<-o} (b + cK).
 
 Everything is complex128 and written for readability, not speed.
 """
@@ -268,6 +275,85 @@ def mpc(U, psi_o, M5, mf, dagger: bool = False, antiperiodic_t: bool = True):
 
 def mdagm(U, psi_o, M5, mf, antiperiodic_t: bool = True):
     return mpc(U, mpc(U, psi_o, M5, mf, False, antiperiodic_t), M5, mf, True, antiperiodic_t)
+
+
+# ----------------------------------------------------------------------------
+# Moebius (Cayley) generalisation
+# ----------------------------------------------------------------------------
+def k5(psi, mf: float, dagger: bool = False):
+    """Fifth-dimension hop (K psi)(s) = P_- psi~(s+1) + P_+ psi~(s-1) (adjoint: P_+ and P_- swapped)."""
+    ls = psi.shape[-3]
+    out = np.zeros_like(psi)
+    for s in range(ls):
+        up = psi[..., s + 1, :, :] if s + 1 < ls else -mf * psi[..., 0, :, :]
+        dn = psi[..., s - 1, :, :] if s >= 1 else -mf * psi[..., ls - 1, :, :]
+        if not dagger:
+            out[..., s, :, :] = _spin(P_MINUS, up) + _spin(P_PLUS, dn)
+        else:
+            out[..., s, :, :] = _spin(P_PLUS, up) + _spin(P_MINUS, dn)
+    return out
+
+
+def mobius_ddw(U, psi, M5, mf, b, c, dagger: bool = False, antiperiodic_t: bool = True):
+    """Moebius D = (b D_W + 1) psi(s) + (c D_W - 1) (K psi)(s) with D_W = (4 - M5) - D_h/2.
+
+    The adjoint is D^dag = (b + c K^dag) D_W^dag + 1 - K^dag.
+    """
+    def dw(f, dag):
+        return (4.0 - M5) * f - 0.5 * dhop(U, f, dag, antiperiodic_t)
+
+    if not dagger:
+        kp = k5(psi, mf)
+        return b * dw(psi, False) + psi + c * dw(kp, False) - kp
+    w = dw(psi, True)
+    return b * w + c * k5(w, mf, True) + psi - k5(psi, mf, True)
+
+
+def mooee(psi, M5, mf, b, c, dagger: bool = False):
+    """Site-local part of D_mob: [b (4-M5) + 1] psi - [1 - c (4-M5)] K psi (adjoint: K^dag)."""
+    return (b * (4.0 - M5) + 1.0) * psi - (1.0 - c * (4.0 - M5)) * k5(psi, mf, dagger)
+
+
+def mooee_inv(psi, M5, mf, b, c, dagger: bool = False):
+    """Mooee^-1 (or Mooee^-dag) by a dense LU solve of the (Ls*4) x (Ls*4) matrix."""
+    ls = psi.shape[-3]
+    k = shift_matrix(ls, mf)
+    kmat = np.kron(k, P_MINUS) + np.kron(k.T, P_PLUS)
+    m = (b * (4.0 - M5) + 1.0) * np.eye(4 * ls) - (1.0 - c * (4.0 - M5)) * kmat
+    if dagger:
+        m = m.conj().T
+    lead = psi.shape[:-3]
+    flat = psi.reshape((-1, ls * 4, 3))
+    rhs = np.moveaxis(flat, 0, 1).reshape(ls * 4, -1)
+    sol = np.linalg.solve(m, rhs)
+    sol = np.moveaxis(sol.reshape(ls * 4, -1, 3), 1, 0)
+    return sol.reshape(lead + (ls, 4, 3))
+
+
+def mobius_mpc(U, psi_o, M5, mf, b, c, dagger: bool = False, antiperiodic_t: bool = True):
+    """Odd-checkerboard Schur complement of D_mob (or its adjoint).
+
+    M_pc     = Mooee     - 1/4 D_h^{o<-e} (b + cK) Mooee^-1 D_h^{e<-o} (b + cK)
+    M_pc^dag = Mooee^dag - 1/4 (b + cK^dag) D_h^dag{o<-e} Mooee^-dag (b + cK^dag) D_h^dag{e<-o}
+    """
+    if not dagger:
+        u = b * psi_o + c * k5(psi_o, mf)
+        t = dhop_cb(U, u, 0, False, antiperiodic_t)
+        t = mooee_inv(t, M5, mf, b, c)
+        t = b * t + c * k5(t, mf)
+        t = dhop_cb(U, t, 1, False, antiperiodic_t)
+        return mooee(psi_o, M5, mf, b, c) - 0.25 * t
+    t = dhop_cb(U, psi_o, 0, True, antiperiodic_t)
+    t = b * t + c * k5(t, mf, True)
+    t = mooee_inv(t, M5, mf, b, c, True)
+    t = dhop_cb(U, t, 1, True, antiperiodic_t)
+    t = b * t + c * k5(t, mf, True)
+    return mooee(psi_o, M5, mf, b, c, True) - 0.25 * t
+
+
+def mobius_mdagm(U, psi_o, M5, mf, b, c, antiperiodic_t: bool = True):
+    return mobius_mpc(U, mobius_mpc(U, psi_o, M5, mf, b, c, False, antiperiodic_t), M5, mf, b, c, True,
+                      antiperiodic_t)
 
 
 # ----------------------------------------------------------------------------

@@ -388,3 +388,102 @@ def test_euclidean_gradient_matches_finite_difference():
     fd = (f(u + h * du) - f(u - h * du)) / (2 * h)
     an = np.sum(np.conj(g) * du).real
     assert abs(fd - an) < 1e-10 * abs(an)
+
+
+# ---------------------------------------------------------------------------
+# Moebius (Cayley) generalisation
+# ---------------------------------------------------------------------------
+B_MOB, C_MOB = 1.5, 0.5
+
+
+def test_mobius_reduces_to_shamir():
+    dims, ls = (2, 4, 2, 4), 5
+    u = F.gauge_field(dims, 0.5, 131)
+    psi = F.fermion_full(dims, ls, 132)
+    po = F.fermion_cb(dims, ls, 133)
+    for dag in (False, True):
+        assert np.abs(R.mobius_ddw(u, psi, M5, MF, 1.0, 0.0, dag) - R.ddw(u, psi, M5, MF, dag)).max() < 1e-13
+        assert np.abs(R.mooee(psi, M5, MF, 1.0, 0.0, dag) - R.m5op(psi, M5, MF, dag)).max() < 1e-13
+        assert np.abs(R.mooee_inv(psi, M5, MF, 1.0, 0.0, dag) - R.m5inv(psi, M5, MF, dag)).max() < 1e-12
+        assert np.abs(R.mobius_mpc(u, po, M5, MF, 1.0, 0.0, dag) - R.mpc(u, po, M5, MF, dag)).max() < 1e-12
+
+
+def _mobius_dense(u, dims, ls, b, c):
+    """The 5D Moebius matrix assembled block by block from a dense D_W, in (s, site, spin, colour)
+    order: (b D_W + 1) on the diagonal, (c D_W - 1) P_- on (s, s+1) and (c D_W - 1) P_+ on
+    (s, s-1), with -mf on the two wraps."""
+    vol = int(np.prod(dims))
+    dw = R.dense_operator(lambda v: R.wilson(u, v, -M5), tuple(dims[::-1]) + (4, 3))
+    n4 = dw.shape[0]
+    one = np.eye(n4)
+    pm = np.kron(np.eye(vol), np.kron(R.P_MINUS, np.eye(3)))
+    pp = np.kron(np.eye(vol), np.kron(R.P_PLUS, np.eye(3)))
+    big = np.zeros((ls * n4, ls * n4), dtype=np.complex128)
+    for s in range(ls):
+        blk = slice(s * n4, (s + 1) * n4)
+        big[blk, blk] += b * dw + one
+        up, fu = (s + 1, 1.0) if s + 1 < ls else (0, -MF)
+        dn, fd = (s - 1, 1.0) if s >= 1 else (ls - 1, -MF)
+        big[blk, up * n4:(up + 1) * n4] += fu * (c * dw - one) @ pm
+        big[blk, dn * n4:(dn + 1) * n4] += fd * (c * dw - one) @ pp
+    return big
+
+
+def test_mobius_matches_dense_bno_blocks():
+    dims, ls = (2, 2, 2, 2), 3
+    u = F.gauge_field(dims, 0.5, 141)
+    big = _mobius_dense(u, dims, ls, B_MOB, C_MOB)
+    psi = F.fermion_full(dims, ls, 142)
+    v = np.moveaxis(psi, 4, 0).ravel()  # (s, site, spin, colour)
+    for dag, m in ((False, big), (True, big.conj().T)):
+        want = np.moveaxis((m @ v).reshape((ls,) + psi.shape[:4] + (4, 3)), 0, 4)
+        got = R.mobius_ddw(u, psi, M5, MF, B_MOB, C_MOB, dag)
+        assert np.abs(got - want).max() < 1e-12
+
+
+def test_mobius_schur_complement_matches_dense_blocks():
+    dims, ls = (2, 2, 2, 2), 3
+    u = F.gauge_field(dims, 0.5, 151)
+    shape = (2, 2, 2, 2, ls, 4, 3)
+    d = R.dense_operator(lambda v: R.mobius_ddw(u, v, M5, MF, B_MOB, C_MOB), shape)
+    par = np.repeat(R.parity(dims).reshape(-1), ls * 12)
+    e, o = np.where(par == 0)[0], np.where(par == 1)[0]
+    schur = d[np.ix_(o, o)] - d[np.ix_(o, e)] @ np.linalg.inv(d[np.ix_(e, e)]) @ d[np.ix_(e, o)]
+    cbshape = (8, ls, 4, 3)
+    mp = R.dense_operator(lambda v: R.mobius_mpc(u, v, M5, MF, B_MOB, C_MOB), cbshape)
+    assert np.abs(mp - schur).max() < 1e-12
+    mpd = R.dense_operator(lambda v: R.mobius_mpc(u, v, M5, MF, B_MOB, C_MOB, dagger=True), cbshape)
+    assert np.abs(mpd - schur.conj().T).max() < 1e-12
+
+
+def test_mobius_adjoints_on_random_fields():
+    dims, ls = (4, 4, 2, 4), 5
+    u = F.gauge_field(dims, 0.5, 161)
+    a = F.fermion_full(dims, ls, 162)
+    b = F.fermion_full(dims, ls, 163)
+    for op, opd in ((lambda f: R.mobius_ddw(u, f, M5, MF, B_MOB, C_MOB),
+                     lambda f: R.mobius_ddw(u, f, M5, MF, B_MOB, C_MOB, True)),
+                    (lambda f: R.k5(f, MF), lambda f: R.k5(f, MF, True)),
+                    (lambda f: R.mooee(f, M5, MF, B_MOB, C_MOB), lambda f: R.mooee(f, M5, MF, B_MOB, C_MOB, True))):
+        lhs = R.vdot(a, op(b))
+        rhs = R.vdot(opd(a), b)
+        assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("b,c", [(1.5, 0.5), (2.0, 1.0), (1.0, 0.0)])
+def test_mooee_inverse_geometric_closed_form(b, c):
+    # Mooee = alpha - beta K with K^Ls = -mf on each chirality, so
+    # Mooee^-1 = (1/beta) sum_n d^-(n+1) K^n / (1 + mf d^-Ls), d = alpha / beta.
+    ls = 6
+    psi = F.fermion_full((2, 2, 2, 2), ls, 171)
+    alpha, beta = b * (4.0 - M5) + 1.0, 1.0 - c * (4.0 - M5)
+    d = alpha / beta
+    for dag in (False, True):
+        acc = np.zeros_like(psi)
+        kp = psi.copy()
+        for n in range(ls):
+            acc += d ** -(n + 1) * kp
+            kp = R.k5(kp, MF, dag)
+        acc /= beta * (1.0 + MF * d ** -ls)
+        assert np.abs(R.mooee_inv(psi, M5, MF, b, c, dag) - acc).max() < 1e-13
+        assert np.abs(R.mooee(R.mooee_inv(psi, M5, MF, b, c, dag), M5, MF, b, c, dag) - psi).max() < 1e-13
