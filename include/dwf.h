@@ -20,6 +20,13 @@
  *     P_+ keeps spins 0,1 and P_- spins 2,3;
  *   D_DW = M5op - D_h/2;  M_pc = M5op - 1/4 D_h^{o<-e} M5op^-1 D_h^{e<-o} on the odd checkerboard.
  *
+ * Moebius (Cayley) form, after dwf_set_mobius(b, c) (not treated in the paper;
+ * the standard Brower-Neff-Orginos operator, b = 1, c = 0 being Shamir):
+ *   K psi(s) = P_- psi~(s+1) + P_+ psi~(s-1);  D_W = (4-M5) - D_h/2;
+ *   D_DW = D_W (b + c K) + 1 - K = Mooee - D_h (b + c K) / 2,
+ *   Mooee = [b (4-M5) + 1] - [1 - c (4-M5)] K, which replaces M5op in dwf_m5;
+ *   M_pc = Mooee - 1/4 D_h^{o<-e} (b + cK) Mooee^-1 D_h^{e<-o} (b + cK).
+ *
  * Canonical layouts (complex FP64, interleaved re,im, DEVICE memory owned by the caller):
  *   gauge        [Lt][Lz][Ly][Lx][4][3][3]      (U[..][mu][a][b], link x -> x+mu)
  *   full field   [Lt][Lz][Ly][Lx][Ls][4][3]
@@ -40,7 +47,8 @@
  *
  * Allocation: dwf_create allocates the link copies and the operator
  * temporaries; dwf_cg / dwf_solve allocate solver workspace on first use;
- * dwf_batch_plan allocates its descriptor tables.  dwf_dhop, dwf_m5, dwf_mpc,
+ * dwf_batch_plan allocates its descriptor tables; dwf_set_mobius allocates one
+ * temporary on the first switch to a Moebius operator.  dwf_dhop, dwf_m5, dwf_mpc,
  * dwf_mdagm, dwf_dw, dwf_axpy and dwf_force never allocate.
  * A context may be used from one host thread at a time.
  */
@@ -102,6 +110,19 @@ int dwf_field_bytes(dwf_ctx ctx, int prec, int full, size_t *bytes);
  * freed afterwards.  Any complex 3x3 matrices are accepted (not only SU(3)). */
 int dwf_set_gauge(dwf_ctx ctx, const double *U, void *stream);
 
+/* Switches the context to the Moebius operator with real coefficients b, c
+ * (b = 1, c = 0 switches back to Shamir; the default).  Afterwards dwf_m5
+ * applies Mooee (and its adjoint and inverse), and dwf_mpc, dwf_mdagm, dwf_dw,
+ * dwf_cg and dwf_solve the Moebius operators defined above; dwf_dhop, dwf_force
+ * and the batch calls concern D_h only and do not change.  M_pc takes three
+ * launches instead of two (the factor b + cK is a site-local kernel), and each
+ * CG iteration a streaming residual update.  Returns DWF_EINVAL for non-finite
+ * b, c or a singular Mooee.  The first switch to a Moebius operator allocates
+ * one FP64 checkerboard temporary; the call synchronises the device. */
+int dwf_set_mobius(dwf_ctx ctx, double b, double c);
+/* The current coefficients (host pointers). */
+int dwf_get_mobius(dwf_ctx ctx, double *b, double *c);
+
 /* Canonical FP64 <-> internal field of precision prec.
  * parity 0 / 1: one checkerboard, canonical [V/2][Ls][4][3];
  * parity 2:     full field, canonical [Lt][Lz][Ly][Lx][Ls][4][3]. */
@@ -118,6 +139,7 @@ int dwf_convert(dwf_ctx ctx, void *out, int out_prec, const void *in, int in_pre
 int dwf_dhop(dwf_ctx ctx, void *out, const void *in, int out_parity, int dagger, int prec, void *stream);
 
 /* out = M5op in, M5op^dag in, M5op^-1 in or M5op^-dag in (dagger, inverse in {0,1});
+ * Mooee in place of M5op for a Moebius context;
  * full = 0: one checkerboard, full = 1: a full field.  in and out may alias. */
 int dwf_m5(dwf_ctx ctx, void *out, const void *in, int dagger, int inverse, int full, int prec, void *stream);
 

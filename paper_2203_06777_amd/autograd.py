@@ -20,9 +20,16 @@ import torch
 from . import dwf as D
 
 
+def _shamir_only(op: D.Context):
+    # the link gradient below differentiates D_h X; a Moebius operator hops (b + cK) X
+    if op.mobius:
+        raise NotImplementedError("autograd: the link gradient is implemented for the Shamir operator only")
+
+
 class DwfOp(torch.autograd.Function):
     @staticmethod
     def forward(ctx, op: D.Context, U: torch.Tensor, x: torch.Tensor):
+        _shamir_only(op)
         U = U.detach().to(torch.complex128).contiguous()
         op.set_gauge(U)
         xi = op.pack(x.detach(), 2, "f64")
@@ -53,6 +60,7 @@ class DwfAction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, op: D.Context, U: torch.Tensor, phi: torch.Tensor, tol: float = 1e-12, maxit: int = 100000,
                 mode: int = 0):
+        _shamir_only(op)
         U = U.detach().to(torch.complex128).contiguous()
         op.set_gauge(U)
         pi = op.pack(phi.detach(), 2, "f64")

@@ -195,6 +195,35 @@ int dwf_field_bytes(dwf_ctx ctx, int prec, int full, size_t *bytes) {
     return DWF_OK;
 }
 
+int dwf_set_mobius(dwf_ctx ctx, double b, double c) {
+    CHECK_CTX(ctx);
+    CHECK(std::isfinite(b) && std::isfinite(c), "dwf_set_mobius: b and c must be finite");
+    Geom g = ctx->g;
+    g.b5 = b;
+    g.c5 = c;
+    g.mobius = !(b == 1.0 && c == 0.0);
+    const double e = mooee_e(g), d = mooee_d(g);
+    CHECK(std::fabs(e) > 1e-12 && std::fabs(d) > 1e-12, "dwf_set_mobius: Mooee = d - e K with d or e = 0");
+    CHECK(std::fabs(1.0 + g.mf * std::pow(d / e, -(double)g.Ls)) > 1e-12,
+          "dwf_set_mobius: 1 + mf (d/e)^-Ls = 0 makes Mooee singular");
+    if (g.mobius && !ctx->tmp[2]) {
+        DWF_HIP(hipDeviceSynchronize());
+        if (hipMalloc(&ctx->tmp[2], cb_bytes(g, DWF_F64)) != hipSuccess)
+            return fail(DWF_ENOMEM, "dwf_set_mobius: hipMalloc of the Moebius temporary failed");
+    }
+    DWF_HIP(hipDeviceSynchronize());  // work queued with the old coefficients finishes first
+    ctx->g = g;
+    return DWF_OK;
+}
+
+int dwf_get_mobius(dwf_ctx ctx, double *b, double *c) {
+    CHECK_CTX(ctx);
+    CHECK(b && c, "dwf_get_mobius: null pointer");
+    *b = ctx->g.b5;
+    *c = ctx->g.c5;
+    return DWF_OK;
+}
+
 int dwf_set_gauge(dwf_ctx ctx, const double *U, void *stream) {
     CHECK_CTX(ctx);
     CHECK(U != nullptr, "dwf_set_gauge: null gauge pointer");
@@ -279,10 +308,27 @@ int dwf_dw(dwf_ctx ctx, void *out, const void *in, int dagger, int prec, void *s
     const char *i = (const char *)in;
     char *o = (char *)out;
     hipStream_t st = (hipStream_t)stream;
+    const Geom &g = ctx->g;
     // out_p = M5op in_p - 1/2 D_h^{p<-1-p} in_{1-p}
+    // Moebius: out_p = Mooee in_p - 1/2 D_h^{p<-1-p} (b + cK) in_{1-p}
+    //          out_p^dag = Mooee^dag in_p + (b + cK^dag) (-1/2 D_h^dag{p<-1-p} in_{1-p})
     for (int p = 0; p < 2; ++p) {
-        DhopCall c{i + (1 - p) * cb, o + p * cb, i + p * cb, p, dagger, EPI_M5, -0.5, 0.0, prec, prec};
-        int rc = launch_dhop(ctx, c, ctx->shape[prec][dagger], st);
+        int rc;
+        if (!g.mobius) {
+            DhopCall c{i + (1 - p) * cb, o + p * cb, i + p * cb, p, dagger, EPI_M5, -0.5, 0.0, prec, prec};
+            rc = launch_dhop(ctx, c, ctx->shape[prec][dagger], st);
+        } else if (!dagger) {
+            if ((rc = launch_m5_op(g, ctx->tmp[2], i + (1 - p) * cb, g.b5, -g.c5, nullptr, 0.0, 0.0, 0, g.half, prec,
+                                   st)))
+                return rc;
+            DhopCall c{ctx->tmp[2], o + p * cb, i + p * cb, p, 0, EPI_M5, -0.5, 0.0, prec, prec};
+            rc = launch_dhop(ctx, c, ctx->shape[prec][0], st);
+        } else {
+            DhopCall c{i + (1 - p) * cb, ctx->tmp[2], nullptr, p, 1, EPI_SCALE, -0.5, 0.0, prec, prec};
+            if ((rc = launch_dhop(ctx, c, ctx->shape[prec][1], st))) return rc;
+            rc = launch_m5_op(g, o + p * cb, i + p * cb, mooee_d(g), mooee_e(g), ctx->tmp[2], g.b5, -g.c5, 1, g.half,
+                              prec, st);
+        }
         if (rc) return rc;
     }
     return DWF_OK;
@@ -353,11 +399,24 @@ int dwf_solve(dwf_ctx ctx, void *x, const void *b, int dagger, double tol, int m
     int rc;
     const char *be = (const char *)b, *bo = be + cb;
     char *xe = (char *)x, *xo = xe + cb;
+    const Geom &g = ctx->g;
+    void *u = ctx->tmp[2];
     // 1. t = M5op^-1 b_e  (into x_e, overwritten at the end)
-    if ((rc = launch_m5(ctx->g, xe, be, dagger, 1, ctx->g.half, DWF_F64, st))) return rc;
+    if ((rc = launch_m5(g, xe, be, dagger, 1, g.half, DWF_F64, st))) return rc;
     // 2. bh = b_o + 1/2 D^{o<-e} t   (into x_o)
-    DhopCall c1{xe, xo, bo, 1, dagger, EPI_AXPY, 0.5, 1.0, DWF_F64, DWF_F64};
-    if ((rc = launch_dhop(ctx, c1, ctx->shape[DWF_F64][dagger], st))) return rc;
+    //    Moebius: bh = b_o + 1/2 D^{o<-e} (b + cK) t;  adjoint: b_o + (b + cK^dag) 1/2 D^dag{o<-e} t
+    if (!g.mobius) {
+        DhopCall c1{xe, xo, bo, 1, dagger, EPI_AXPY, 0.5, 1.0, DWF_F64, DWF_F64};
+        if ((rc = launch_dhop(ctx, c1, ctx->shape[DWF_F64][dagger], st))) return rc;
+    } else if (!dagger) {
+        if ((rc = launch_m5_op(g, u, xe, g.b5, -g.c5, nullptr, 0.0, 0.0, 0, g.half, DWF_F64, st))) return rc;
+        DhopCall c1{u, xo, bo, 1, 0, EPI_AXPY, 0.5, 1.0, DWF_F64, DWF_F64};
+        if ((rc = launch_dhop(ctx, c1, ctx->shape[DWF_F64][0], st))) return rc;
+    } else {
+        DhopCall c1{xe, u, nullptr, 1, 1, EPI_SCALE, 0.5, 0.0, DWF_F64, DWF_F64};
+        if ((rc = launch_dhop(ctx, c1, ctx->shape[DWF_F64][1], st))) return rc;
+        if ((rc = launch_m5_op(g, xo, bo, 1.0, 0.0, u, g.b5, -g.c5, 1, g.half, DWF_F64, st))) return rc;
+    }
     dwf_cg_stats s{0, 0, 0.0, 0.0};
     if (!dagger) {
         // 3. rhs = M_pc^dag bh (into x_e slot), x_o = CG solution from zero
@@ -374,8 +433,21 @@ int dwf_solve(dwf_ctx ctx, void *x, const void *b, int dagger, double tol, int m
         if (rc2) return rc2;
     }
     // 4. x_e = M5op^-1 (b_e + 1/2 D^{e<-o} x_o)
-    DhopCall c2{xo, xe, be, 0, dagger, EPI_M5INV, 0.5, 1.0, DWF_F64, DWF_F64};
-    int rc3 = launch_dhop(ctx, c2, ctx->shape[DWF_F64][dagger], st);
+    //    Moebius: Mooee^-1 (b_e + 1/2 D^{e<-o} (b + cK) x_o);  adjoint: Mooee^-dag (b_e + (b + cK^dag) 1/2 D^dag{e<-o} x_o)
+    int rc3;
+    if (!g.mobius) {
+        DhopCall c2{xo, xe, be, 0, dagger, EPI_M5INV, 0.5, 1.0, DWF_F64, DWF_F64};
+        rc3 = launch_dhop(ctx, c2, ctx->shape[DWF_F64][dagger], st);
+    } else if (!dagger) {
+        if ((rc3 = launch_m5_op(g, u, xo, g.b5, -g.c5, nullptr, 0.0, 0.0, 0, g.half, DWF_F64, st))) return rc3;
+        DhopCall c2{u, xe, be, 0, 0, EPI_M5INV, 0.5, 1.0, DWF_F64, DWF_F64};
+        rc3 = launch_dhop(ctx, c2, ctx->shape[DWF_F64][0], st);
+    } else {
+        DhopCall c2{xo, u, nullptr, 0, 1, EPI_SCALE, 0.5, 0.0, DWF_F64, DWF_F64};
+        if ((rc3 = launch_dhop(ctx, c2, ctx->shape[DWF_F64][1], st))) return rc3;
+        if ((rc3 = launch_m5_op(g, u, be, 1.0, 0.0, u, g.b5, -g.c5, 1, g.half, DWF_F64, st))) return rc3;
+        rc3 = launch_m5(g, xe, u, 1, 1, g.half, DWF_F64, st);
+    }
     if (rc3) return rc3;
     DWF_HIP(hipStreamSynchronize(st));
     if (stats) *stats = s;

@@ -132,15 +132,24 @@ DhopShape default_shape(const Geom &g) {
     return sh;
 }
 
-void m5inv_coefficients(const Geom &g, double *coef) {
-    const double d = 5.0 - g.M5;
+// Mooee = d - e K:  Mooee^-1 = sum_n coef[n] K^n with coef[n] = q^-(n+1) / (e (1 + mf q^-Ls)),
+// q = d / e.  The Schur factor Mooee^-1 (b + c K) = -(c/e) + (b + c d/e) Mooee^-1 (b + c K
+// differs from Mooee by a multiple of the identity), so only its coefficients change.  For
+// Shamir (e = 1, b = 1, c = 0) both tables are the plain M5op^-1 one, bit for bit.
+void m5inv_coefficients(const Geom &g, double *coef, bool schur) {
+    const double e = mooee_e(g), d = mooee_d(g) / e;
     double dn = 1.0;
     for (int n = 0; n < g.Ls; ++n) dn /= d;  // d^-Ls
-    const double norm = 1.0 / (1.0 + g.mf * dn);
+    const double norm = 1.0 / (1.0 + g.mf * dn) / e;
     double p = 1.0 / d;
     for (int n = 0; n < kMaxLs; ++n) {
         coef[n] = n < g.Ls ? p * norm : 0.0;
         p /= d;
+    }
+    if (schur && g.mobius) {
+        const double f = g.b5 + g.c5 * d;
+        for (int n = 0; n < g.Ls; ++n) coef[n] *= f;
+        coef[0] -= g.c5 / e;
     }
 }
 
@@ -208,7 +217,8 @@ bool fill_dhop_args(dwf_ctx ctx, const DhopShape &shape, int prec_in, int out_pa
     a.xcd = shape.xcd;
     a.nt_store = shape.nt_store;
     a.alpha = 1.0;
-    a.d5 = 5.0 - g.M5;
+    a.d5 = mooee_d(g);
+    a.e5 = mooee_e(g);
     a.mf = g.mf;
     m5inv_coefficients(g, a.coef);
     const bool rows_mode = shape.rows > 0 && row_shape_ok(g, shape, prec_in, ctx->lds_limit);
@@ -246,6 +256,7 @@ int launch_dhop(dwf_ctx ctx, const DhopCall &c, const DhopShape &shape_in, hipSt
     a.norm_out = (c.epi == EPI_M5 || c.epi == EPI_CG) ? c.norm_out : nullptr;
     a.cg_alpha = c.cg_alpha;
     a.cg_live = c.cg_live;
+    if (c.schur_coef) m5inv_coefficients(g, a.coef, true);
     if (c.epi == EPI_CG && (!c.norm_out || !c.cg_alpha || !c.cg_live || !c.z))
         return fail(DWF_EINVAL, "hopping kernel: CG epilogue needs z, partials and the solver scalars");
     int threads;

@@ -49,7 +49,15 @@ struct Geom {
     long half;  // vol / 2
     double M5, mf;
     int antiperiodic;
+    // Moebius (Cayley) coefficients: D = D_W(-M5) (b + c K) + 1 - K with the
+    // fifth-dimension hop K; mobius == 0 means b = 1, c = 0 (Shamir).
+    double b5 = 1.0, c5 = 0.0;
+    int mobius = 0;
 };
+
+// Site-local part Mooee = d - e K (Shamir: d = 5 - M5, e = 1).
+inline double mooee_d(const Geom &g) { return g.mobius ? g.b5 * (4.0 - g.M5) + 1.0 : 5.0 - g.M5; }
+inline double mooee_e(const Geom &g) { return g.mobius ? 1.0 - g.c5 * (4.0 - g.M5) : 1.0; }
 
 // Bytes of one internal checkerboard field.
 inline size_t cb_bytes(const Geom &g, int prec) { return (size_t)g.half * g.Ls * 24 * real_bytes(prec); }
@@ -73,8 +81,9 @@ constexpr int kMaxDhopThreads = 512;
 enum Epi {
     EPI_SCALE = 0,  // out = alpha * D psi
     EPI_AXPY = 1,   // out = beta * z + alpha * D psi
-    EPI_M5 = 2,     // out = M5op(z) + alpha * D psi   (M5op^dag when dagger)
-    EPI_M5INV = 3,  // out = M5op^-1 (beta * z + alpha * D psi)   (M5op^-dag when dagger; z optional)
+    EPI_M5 = 2,     // out = Mooee(z) + alpha * D psi   (Mooee^dag when dagger; Mooee = M5op for Shamir)
+    EPI_M5INV = 3,  // out = Mooee^-1 (beta * z + alpha * D psi)   (Mooee^-dag when dagger; z optional);
+                    // with DhopCall::schur_coef the Schur factor Mooee^-1 (b + c K) instead
     EPI_CG = 4,     // CG step: y = M5op(z) + alpha * D psi is A p; out (= r, FP32 or FP64, read and
                     // written) -= (*cg_alpha) * y when *cg_live != 0, with |r|^2 partials in norm_out
 };
@@ -91,6 +100,7 @@ struct DhopCall {
     double *norm_out = nullptr;  // EPI_M5, EPI_CG: per-workgroup partial sums of |out|^2 (FP64, fixed order)
     long *nparts_out = nullptr;  // receives the number of partials written
     const double *cg_alpha = nullptr, *cg_live = nullptr;  // EPI_CG: device scalars of the solver
+    bool schur_coef = false;     // EPI_M5INV: apply Mooee^-1 (b + c K) (identical to Mooee^-1 for Shamir)
 };
 
 // Solver workspace (allocated on first solve).
@@ -108,7 +118,7 @@ struct dwf_ctx_s {
     int device = 0;
     void *links[4][2] = {};  // [prec][output parity]
     bool gauge_set = false;
-    void *tmp[2] = {};       // FP64-sized checkerboard temporaries for M_pc
+    void *tmp[3] = {};       // FP64-sized checkerboard temporaries for M_pc (tmp[2]: Moebius only)
     double *partials = nullptr;  // reduction partials (2 * kRedBlocks doubles)
     double *dhop_partials = nullptr;  // one FP64 partial per hopping-kernel workgroup (V/2 doubles)
     double *scal = nullptr;      // device scalars of the solvers
@@ -152,7 +162,11 @@ bool row_shape_ok(const Geom &g, const DhopShape &sh, int prec, size_t lds_limit
 // M5op family on ncb checkerboard fields (m5.hip).
 int launch_m5(const Geom &g, void *out, const void *in, int dagger, int inverse, long nsites, int prec,
               hipStream_t st);
-void m5inv_coefficients(const Geom &g, double *coef);
+// out = (d x + db z) - K (e x + eb z)  (K^dag when dagger; z optional, out may alias z).
+int launch_m5_op(const Geom &g, void *out, const void *x, double d, double e, const void *z, double db, double eb,
+                 int dagger, long nsites, int prec, hipStream_t st);
+// Coefficients of Mooee^-1 = sum_n coef[n] K^n; with schur, of Mooee^-1 (b + c K).
+void m5inv_coefficients(const Geom &g, double *coef, bool schur = false);
 
 // BLAS-1 and reductions (blas.hip). n = number of complex elements.
 int launch_reduce(double *partials, double *dst, const void *x, const void *y, long n, int prec, int dot,
@@ -169,6 +183,9 @@ int op_mpcdag_cg(dwf_ctx ctx, void *r, int prec_r, const void *y, int prec, cons
                  const double *cg_live, double *partials, long *nparts, hipStream_t st);
 
 // Solvers (solver.hip).
+// r (prec_r) -= (*cg_alpha) w (prec_w) when *cg_live != 0, with |r|^2 partials (count in *nparts).
+int launch_cg_residual(dwf_ctx ctx, void *r, int prec_r, const void *w, int prec_w, const double *cg_alpha,
+                       const double *cg_live, double *partials, long *nparts, hipStream_t st);
 int cg_solve(dwf_ctx ctx, void *x, const void *b, double tol, int maxit, int mode, dwf_cg_stats *stats,
              hipStream_t st);
 

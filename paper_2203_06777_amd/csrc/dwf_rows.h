@@ -32,7 +32,7 @@ struct DhopArgs {
     unsigned nrows, ty, tz, tt, nty, ntt;
     unsigned lds_pad;  // host side: minimum LDS request of the row kernel (residency cap)
     float inv_per, inv_ty, inv_tz, inv_ntt, inv_ntyt;
-    double alpha, beta, d5, mf;
+    double alpha, beta, d5, e5, mf;  // Mooee = d5 - e5 K
     double *norm_out;
     const double *cg_alpha, *cg_live;
     double coef[kMaxLs];
@@ -105,8 +105,9 @@ __device__ __forceinline__ void m5_combine(const DhopArgs &a, Off zoff, int Ls, 
     load_spinor_off<PI>(a.z, zoff, Ls * 16, z0);
     load_spinor_off<PI>(a.z, row + (Off)((s + 1 < Ls ? s + 1 : 0) * 16), Ls * 16, zu);
     load_spinor_off<PI>(a.z, row + (Off)((s >= 1 ? s - 1 : Ls - 1) * 16), Ls * 16, zd);
-    const A fu = s + 1 < Ls ? (A)1 : (A)(-a.mf);
-    const A fd = s >= 1 ? (A)1 : (A)(-a.mf);
+    // e5 (1 for Shamir) folded into the shift factors
+    const A fu = (A)(s + 1 < Ls ? a.e5 : -a.mf * a.e5);
+    const A fd = (A)(s >= 1 ? a.e5 : -a.mf * a.e5);
     const A d5 = (A)a.d5, alpha = (A)a.alpha;
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = d5 * z0[k] - (DAG ? fu * zu[k] : fd * zd[k]) + alpha * acc[k];

@@ -1,20 +1,23 @@
-// Fifth-dimension (Shamir) term on its own: M5op, M5op^dag, M5op^-1, M5op^-dag.
+// Fifth-dimension term on its own: Mooee = d - e K and its adjoint and inverse
+// (Shamir: d = 5 - M5, e = 1, i.e. M5op), and the general site-local
+// combination (d x + db z) - K (e x + eb z) the Moebius operator needs.
 //
 // One lane per (4D site, s); the Ls lanes of a site exchange their spinors
-// through LDS, so the kernel reads and writes each field once and in == out
-// is allowed.  M5op couples s to s +- 1 (P_- to s+1, P_+ to s-1, with -mf on
-// the wraps); its inverse is, per chirality, the geometric series of the
-// twisted shift K (K^Ls = -mf):  (d - K)^-1 = sum_n d^-(n+1) K^n / (1 + mf d^-Ls).
+// through LDS, so the kernel reads and writes each field once and out may
+// alias an input.  K couples s to s +- 1 (P_- to s+1, P_+ to s-1, with -mf on
+// the wraps); the inverse is, per chirality, the geometric series of the
+// twisted shift K (K^Ls = -mf):
+//   (d - e K)^-1 = (1/e) sum_n q^-(n+1) K^n / (1 + mf q^-Ls),  q = d / e.
 #include "dwf_device.h"
 
 namespace dwf {
 
 struct M5Args {
-    const u32x4 *in;
+    const u32x4 *in, *in2;  // x, z (z may be null)
     u32x4 *out;
     long nsites;
     int Ls, spb, dagger, inverse;
-    double d5, mf;
+    double d, e, db, eb, mf;
     double coef[kMaxLs];
 };
 
@@ -28,14 +31,37 @@ __global__ void __launch_bounds__(1024) k_m5(const M5Args a) {
     const int s = threadIdx.x - j * Ls;
     const long c = (long)blockIdx.x * a.spb + j;
     const bool active = c < a.nsites;
-    A v[24];
+    A v[24], w[24];
     if (active) load_spinor<P>(a.in, c, Ls, s, v);
     else
 #pragma unroll
         for (int k = 0; k < 24; ++k) v[k] = 0;
+    if (a.inverse) {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) w[k] = v[k];
+    } else {
+        // own term d x (+ db z) and the shifted one e x (+ eb z)
+        const A d = (A)a.d, e = (A)a.e;
+        if (a.in2 && active) {
+            A z[24];
+            load_spinor<P>(a.in2, c, Ls, s, z);
+            const A db = (A)a.db, eb = (A)a.eb;
+#pragma unroll
+            for (int k = 0; k < 24; ++k) {
+                w[k] = e * v[k] + eb * z[k];
+                v[k] = d * v[k] + db * z[k];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 24; ++k) {
+                w[k] = e * v[k];
+                v[k] = d * v[k];
+            }
+        }
+    }
     A *mine = lds + (j * Ls + s) * 25;
 #pragma unroll
-    for (int k = 0; k < 24; ++k) mine[k] = v[k];
+    for (int k = 0; k < 24; ++k) mine[k] = w[k];
     __syncthreads();
     if (!active) return;
     const A *site = lds + j * Ls * 25;
@@ -45,12 +71,11 @@ __global__ void __launch_bounds__(1024) k_m5(const M5Args a) {
         const int su = s + 1 < Ls ? s + 1 : 0, sd = s >= 1 ? s - 1 : Ls - 1;
         const A fu = s + 1 < Ls ? (A)1 : -mf, fd = s >= 1 ? (A)1 : -mf;
         const A *zu = site + su * 25, *zd = site + sd * 25;
-        const A d5 = (A)a.d5;
         // upper spins: P_+ takes s-1 (adjoint: s+1); lower spins: P_- takes s+1 (adjoint: s-1)
 #pragma unroll
-        for (int k = 0; k < 12; ++k) o[k] = d5 * v[k] - (a.dagger ? fu * zu[k] : fd * zd[k]);
+        for (int k = 0; k < 12; ++k) o[k] = v[k] - (a.dagger ? fu * zu[k] : fd * zd[k]);
 #pragma unroll
-        for (int k = 12; k < 24; ++k) o[k] = d5 * v[k] - (a.dagger ? fd * zd[k] : fu * zu[k]);
+        for (int k = 12; k < 24; ++k) o[k] = v[k] - (a.dagger ? fd * zd[k] : fu * zu[k]);
     } else {
 #pragma unroll
         for (int k = 0; k < 24; ++k) o[k] = 0;
@@ -74,19 +99,11 @@ __global__ void __launch_bounds__(1024) k_m5(const M5Args a) {
     store_spinor<P>(a.out, c, Ls, s, o);
 }
 
-int launch_m5(const Geom &g, void *out, const void *in, int dagger, int inverse, long nsites, int prec,
-              hipStream_t st) {
-    M5Args a;
-    a.in = (const u32x4 *)in;
-    a.out = (u32x4 *)out;
+static int launch_m5_args(const Geom &g, M5Args &a, long nsites, int prec, hipStream_t st) {
     a.nsites = nsites;
     a.Ls = g.Ls;
     a.spb = default_shape(g).spb;
-    a.dagger = dagger;
-    a.inverse = inverse;
-    a.d5 = 5.0 - g.M5;
     a.mf = g.mf;
-    m5inv_coefficients(g, a.coef);
     const int threads = a.spb * g.Ls;
     const unsigned nb = (unsigned)((nsites + a.spb - 1) / a.spb);
     const size_t areal = prec == DWF_F64 ? 8 : 4;
@@ -99,6 +116,37 @@ int launch_m5(const Geom &g, void *out, const void *in, int dagger, int inverse,
     }
     DWF_HIP(hipGetLastError());
     return DWF_OK;
+}
+
+int launch_m5(const Geom &g, void *out, const void *in, int dagger, int inverse, long nsites, int prec,
+              hipStream_t st) {
+    M5Args a;
+    a.in = (const u32x4 *)in;
+    a.in2 = nullptr;
+    a.out = (u32x4 *)out;
+    a.dagger = dagger;
+    a.inverse = inverse;
+    a.d = mooee_d(g);
+    a.e = mooee_e(g);
+    a.db = a.eb = 0.0;
+    m5inv_coefficients(g, a.coef);
+    return launch_m5_args(g, a, nsites, prec, st);
+}
+
+int launch_m5_op(const Geom &g, void *out, const void *x, double d, double e, const void *z, double db, double eb,
+                 int dagger, long nsites, int prec, hipStream_t st) {
+    M5Args a;
+    a.in = (const u32x4 *)x;
+    a.in2 = (const u32x4 *)z;
+    a.out = (u32x4 *)out;
+    a.dagger = dagger;
+    a.inverse = 0;
+    a.d = d;
+    a.e = e;
+    a.db = db;
+    a.eb = eb;
+    for (int n = 0; n < kMaxLs; ++n) a.coef[n] = 0.0;
+    return launch_m5_args(g, a, nsites, prec, st);
 }
 
 }  // namespace dwf

@@ -136,6 +136,42 @@ __global__ void __launch_bounds__(256) k_axpy_f32_to_f64(u32x4 *y, const u32x4 *
     store_spinor<DWF_F64>(y, c, Ls, s, yv);
 }
 
+// r (PR) -= alpha * w (PW) when the iteration is live, with one FP64 partial of
+// the new |r|^2 per workgroup (fixed-order LDS tree); the streaming form of the
+// CG epilogue for operators whose last factor is not a hopping kernel.
+template <int PR, int PW>
+__global__ void __launch_bounds__(256) k_cg_residual(u32x4 *r, const u32x4 *w, const double *cg_alpha,
+                                                     const double *cg_live, double *partials, long nrows, int Ls) {
+    if (*cg_live == 0) return;  // the sums are ignored when the iteration is not live
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    const bool active = t < nrows * Ls;
+    using RA = typename PT<PR>::A;
+    double part = 0;
+    if (active) {
+        const long c = t / Ls;
+        const int s = (int)(t - c * Ls);
+        RA rv[24];
+        typename PT<PW>::A wv[24];
+        load_spinor<PR>(r, c, Ls, s, rv);
+        load_spinor<PW>(w, c, Ls, s, wv);
+        const RA ca = (RA)*cg_alpha;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) {
+            rv[k] = rv[k] - ca * (RA)wv[k];
+            part += (double)rv[k] * (double)rv[k];
+        }
+        store_spinor<PR>(r, c, Ls, s, rv);
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = part;
+    __syncthreads();
+    for (int stride = 128; stride > 0; stride >>= 1) {
+        if ((int)threadIdx.x < stride) red[threadIdx.x] += red[threadIdx.x + stride];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
 __global__ void k_set_scalars(double *scal, double stop) {
     if (threadIdx.x != 0) return;
     scal[S_RR] = scal[S_RED];
@@ -146,6 +182,25 @@ __global__ void k_set_scalars(double *scal, double stop) {
 }
 
 static inline unsigned nb256(long n) { return (unsigned)((n + 255) / 256); }
+
+int launch_cg_residual(dwf_ctx ctx, void *r, int prec_r, const void *w, int prec_w, const double *cg_alpha,
+                       const double *cg_live, double *partials, long *nparts, hipStream_t st) {
+    const Geom &g = ctx->g;
+    const unsigned nb = nb256(g.half * g.Ls);
+    if (nparts) *nparts = nb;
+    u32x4 *r4 = (u32x4 *)r;
+    const u32x4 *w4 = (const u32x4 *)w;
+#define DWF_RES(PR, PW) hipLaunchKernelGGL((k_cg_residual<PR, PW>), nb, 256, 0, st, r4, w4, cg_alpha, cg_live, \
+                                           partials, g.half, g.Ls)
+    if (prec_r == DWF_F64 && prec_w == DWF_F64) DWF_RES(DWF_F64, DWF_F64);
+    else if (prec_r == DWF_F32 && prec_w == DWF_F32) DWF_RES(DWF_F32, DWF_F32);
+    else if (prec_r == DWF_F32 && prec_w == DWF_F16) DWF_RES(DWF_F32, DWF_F16);
+    else if (prec_r == DWF_F32 && prec_w == DWF_BF16) DWF_RES(DWF_F32, DWF_BF16);
+    else return fail(DWF_EUNSUP, "CG residual update: unsupported precision pair");
+#undef DWF_RES
+    DWF_HIP(hipGetLastError());
+    return DWF_OK;
+}
 
 static int ensure_work(dwf_ctx ctx) {
     CgWork &w = ctx->work;

@@ -52,6 +52,8 @@ _SIGS = {
     "dwf_destroy": [_P],
     "dwf_field_bytes": [_P, _I, _I, ctypes.POINTER(ctypes.c_size_t)],
     "dwf_set_gauge": [_P, _P, _P],
+    "dwf_set_mobius": [_P, _D, _D],
+    "dwf_get_mobius": [_P, ctypes.POINTER(_D), ctypes.POINTER(_D)],
     "dwf_pack": [_P, _P, _P, _I, _I, _P],
     "dwf_unpack": [_P, _P, _P, _I, _I, _P],
     "dwf_convert": [_P, _P, _I, _P, _I, _I, _P],
@@ -137,6 +139,16 @@ def dwf_field_bytes(ctx, prec, full=0) -> int:
     n = ctypes.c_size_t()
     _check(lib().dwf_field_bytes(ctx, _prec(prec), int(full), ctypes.byref(n)))
     return n.value
+
+
+def dwf_set_mobius(ctx, b, c):
+    _check(lib().dwf_set_mobius(ctx, float(b), float(c)))
+
+
+def dwf_get_mobius(ctx):
+    b, c = _D(), _D()
+    _check(lib().dwf_get_mobius(ctx, ctypes.byref(b), ctypes.byref(c)))
+    return b.value, c.value
 
 
 def dwf_set_gauge(ctx, U, stream=None):
@@ -286,6 +298,15 @@ class Context:
         """Views of the even and odd checkerboards of a full internal field."""
         n = full_field.numel() // 2
         return full_field[:n], full_field[n:]
+
+    def set_mobius(self, b: float, c: float):
+        """Moebius coefficients (b = 1, c = 0 is Shamir, the default)."""
+        dwf_set_mobius(self.handle, b, c)
+
+    @property
+    def mobius(self) -> bool:
+        b, c = dwf_get_mobius(self.handle)
+        return not (b == 1.0 and c == 0.0)
 
     def set_gauge(self, U: torch.Tensor):
         dwf_set_gauge(self.handle, U.to(torch.complex128).contiguous())
