@@ -267,6 +267,36 @@ def main():
             r[nm]["speedup_vs_fp64"] = round(r["fp64"]["seconds"] / r[nm]["seconds"], 3)
         rows["cg_24^4x12"] = r
         log(f"row cg: {r}")
+
+        # Moebius (Cayley) operator, b = 1.5, c = 0.5, on the same lattice, gauge and right-hand side
+        if row_on("mobius_24^4x12"):
+            rm = {"b": 1.5, "c": 0.5}
+            tmp = op2.field("f32")
+            p32 = op2.field("f32")
+            D.dwf_convert(op2.handle, p32, "f32", bi, "f64", 0)
+            rm["shamir_mdagm_f32_us"] = round(timed(lambda: D.dwf_mdagm(op2.handle, tmp, p32, "f32"), 20) * 1e3, 1)
+            op2.set_mobius(1.5, 0.5)
+            rm["mobius_mdagm_f32_us"] = round(timed(lambda: D.dwf_mdagm(op2.handle, tmp, p32, "f32"), 20) * 1e3, 1)
+            msol = {}
+            for mode in (0, 2):
+                D.dwf_cg(op2.handle, op2.zeros("f64"), bi, 1e-2, 50000, mode)
+            for mode, nm in ((0, "fp64"), (2, "mixed_fp16")):
+                x = op2.zeros("f64")
+                torch.cuda.synchronize()
+                t = time.time()
+                st = D.dwf_cg(op2.handle, x, bi, w["tol"], 50000, mode)
+                torch.cuda.synchronize()
+                msol[mode] = x
+                rm[nm] = {"seconds": round(time.time() - t, 4), "iters": st["inner_iters"], "outer": st["outer_iters"],
+                          "true_rel_resid": st["true_rel_resid"]}
+            d = op2.field("f64")
+            d.copy_(msol[2])
+            D.dwf_axpy(op2.handle, d, -1.0, msol[0], 0, "f64")
+            rm["mixed_fp16"]["rel_l2_vs_fp64"] = float(
+                np.sqrt(D.dwf_norm2(op2.handle, d, 0, "f64") / D.dwf_norm2(op2.handle, msol[0], 0, "f64")))
+            rm["mixed_fp16"]["speedup_vs_fp64"] = round(rm["fp64"]["seconds"] / rm["mixed_fp16"]["seconds"], 3)
+            rows["mobius_24^4x12"] = rm
+            log(f"row mobius: {rm}")
         op2.close()
         del sol, bi, u2, b
         torch.cuda.empty_cache()
