@@ -43,8 +43,11 @@ struct DhopArgs {
 // applies to this shape (otherwise the site kernel does).
 bool fill_dhop_args(dwf_ctx ctx, const DhopShape &shape, int prec_in, int out_parity, DhopArgs &a);
 
-// partials[blockIdx.x] = sum over the workgroup's active lanes of |v|^2, by a
-// fixed LDS tree (bitwise reproducible).  Every lane of the workgroup calls it.
+// partials[blockIdx.x] = sum over the workgroup's active lanes of |v|^2 in a
+// fixed order (bitwise reproducible): a wavefront shuffle tree, then the wave
+// sums in wave order.  A workgroup whose size is not a multiple of 64 has a
+// partial last wave whose missing lanes a shuffle must not read; it sums
+// through an LDS tree instead.  Every lane of the workgroup calls it.
 template <typename A>
 __device__ __forceinline__ void block_norm_partial(double *partials, const A *v, bool active) {
     __shared__ double red[kMaxDhopThreads];
@@ -53,6 +56,18 @@ __device__ __forceinline__ void block_norm_partial(double *partials, const A *v,
 #pragma unroll
         for (int k = 0; k < 24; ++k) x += (double)v[k] * (double)v[k];
     const int t = threadIdx.x, n = blockDim.x;
+    if ((n & 63) == 0) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+        if ((t & 63) == 0) red[t >> 6] = x;
+        __syncthreads();
+        if (t == 0) {
+            double sum = 0;
+            for (int w = 0; w < (n >> 6); ++w) sum += red[w];
+            partials[blockIdx.x] = sum;
+        }
+        return;
+    }
     red[t] = x;
     __syncthreads();
     for (int stride = kMaxDhopThreads / 2; stride > 0; stride >>= 1) {

@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(256) k_axpy_f32_to_f64(u32x4 *y, const u32x4 *
 }
 
 // r (PR) -= alpha * w (PW) when the iteration is live, with one FP64 partial of
-// the new |r|^2 per workgroup (fixed-order LDS tree); the streaming form of the
+// the new |r|^2 per workgroup (fixed-order shuffle tree); the streaming form of the
 // CG epilogue for operators whose last factor is not a hopping kernel.
 template <int PR, int PW>
 __global__ void __launch_bounds__(256) k_cg_residual(u32x4 *r, const u32x4 *w, const double *cg_alpha,
@@ -162,14 +162,13 @@ __global__ void __launch_bounds__(256) k_cg_residual(u32x4 *r, const u32x4 *w, c
         }
         store_spinor<PR>(r, c, Ls, s, rv);
     }
-    __shared__ double red[256];
-    red[threadIdx.x] = part;
+    // wavefront shuffle tree, then the four wave sums in order
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) part += __shfl_xor(part, off, 64);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
     __syncthreads();
-    for (int stride = 128; stride > 0; stride >>= 1) {
-        if ((int)threadIdx.x < stride) red[threadIdx.x] += red[threadIdx.x + stride];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 __global__ void k_set_scalars(double *scal, double stop) {
