@@ -483,6 +483,43 @@ def force_su3(U, X, Y, antiperiodic_t=True):
 
 
 # ----------------------------------------------------------------------------
+# Hybrid Monte Carlo molecular dynamics with the pseudofermion action
+# ----------------------------------------------------------------------------
+def expi(q, eps):
+    """exp(i eps Q) for Hermitian Q [..., 3, 3], by its eigen-decomposition."""
+    w, v = np.linalg.eigh(q)
+    return np.einsum("...ik,...k,...jk->...ij", v, np.exp(1j * eps * w), v.conj())
+
+
+def action_and_force(U, phi, M5, mf, tol=1e-13, antiperiodic_t=True):
+    """S = phi^dag (D^dag D)^-1 phi and its su(3) force K: under U -> exp(i eps Q) U the
+    action changes by eps sum tr(Q K) + O(eps^2)."""
+    s, x = action_cg(U, phi, M5, mf, tol=tol, antiperiodic_t=antiperiodic_t)
+    y = ddw(U, x, M5, mf, False, antiperiodic_t)
+    return s, force_su3(U, x, y, antiperiodic_t)
+
+
+def hamiltonian(U, P, phi, M5, mf, tol=1e-13, antiperiodic_t=True):
+    """H = sum_links tr(P^2) + S(U) for traceless Hermitian momenta P = sum_a omega_a lambda_a / 2,
+    whose Gaussian weight exp(-sum omega^2 / 2) is exp(-sum tr P^2)."""
+    s, _ = action_and_force(U, phi, M5, mf, tol, antiperiodic_t)
+    return float(np.sum(np.einsum("...ij,...ji->...", P, P)).real) + s
+
+
+def leapfrog(U, P, phi, M5, mf, eps, nsteps, tol=1e-13, antiperiodic_t=True):
+    """nsteps leapfrog steps of the equations that conserve H: dU/dtau = i P U and
+    dP/dtau = -K(U)/2 (d tr P^2 = -tr(P K) dtau cancels dS = tr(P K) dtau).  A half step
+    of P, alternating full steps of U and P, and a closing half step of P.  Returns (U, P)."""
+    _, k = action_and_force(U, phi, M5, mf, tol, antiperiodic_t)
+    P = P - 0.25 * eps * k
+    for n in range(nsteps):
+        U = expi(P, eps) @ U
+        _, k = action_and_force(U, phi, M5, mf, tol, antiperiodic_t)
+        P = P - (0.5 * eps if n + 1 < nsteps else 0.25 * eps) * k
+    return U, P
+
+
+# ----------------------------------------------------------------------------
 # Dense matrices (brute force on tiny lattices)
 # ----------------------------------------------------------------------------
 def dense_operator(apply, shape):

@@ -487,3 +487,48 @@ def test_mooee_inverse_geometric_closed_form(b, c):
         acc /= beta * (1.0 + MF * d ** -ls)
         assert np.abs(R.mooee_inv(psi, M5, MF, b, c, dag) - acc).max() < 1e-13
         assert np.abs(R.mooee(R.mooee_inv(psi, M5, MF, b, c, dag), M5, MF, b, c, dag) - psi).max() < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Hybrid Monte Carlo molecular dynamics
+# ---------------------------------------------------------------------------
+def test_expi_is_the_matrix_exponential_in_su3():
+    from scipy.linalg import expm
+
+    q = F.su3_directions((2, 2, 2, 2), 701)
+    e = R.expi(q, 0.37)
+    want = np.array([expm(0.37j * m) for m in q.reshape(-1, 3, 3)]).reshape(e.shape)
+    assert np.abs(e - want).max() < 1e-14
+    eye = np.eye(3)
+    assert np.abs(np.conj(np.swapaxes(e, -1, -2)) @ e - eye).max() < 1e-14
+    assert np.abs(np.linalg.det(e) - 1.0).max() < 1e-14
+
+
+def _md_case():
+    dims, ls = (2, 2, 2, 4), 3
+    u = F.gauge_field(dims, 0.5, 711)
+    phi = F.fermion_full(dims, ls, 712)
+    p = F.su3_directions(dims, 713)
+    return u, p, phi
+
+
+def test_leapfrog_is_reversible():
+    u, p, phi = _md_case()
+    u1, p1 = R.leapfrog(u, p, phi, M5, MF, 0.1, 3)
+    u2, p2 = R.leapfrog(u1, -p1, phi, M5, MF, 0.1, 3)
+    assert np.abs(u2 - u).max() < 1e-10
+    assert np.abs(-p2 - p).max() < 1e-10
+    assert np.abs(u1 - u).max() > 1e-2  # it moved
+
+
+def test_leapfrog_energy_violation_is_second_order():
+    # over a fixed trajectory length the leapfrog error in H is O(eps^2)
+    u, p, phi = _md_case()
+    h0 = R.hamiltonian(u, p, phi, M5, MF)
+    dh = []
+    for eps, n in ((0.1, 4), (0.05, 8)):
+        u1, p1 = R.leapfrog(u, p, phi, M5, MF, eps, n)
+        dh.append(R.hamiltonian(u1, p1, phi, M5, MF) - h0)
+    ratio = dh[0] / dh[1]
+    assert 3.3 < ratio < 4.7, dh
+    assert abs(dh[0]) < 1e-2 * abs(h0)
