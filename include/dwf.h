@@ -193,6 +193,21 @@ int dwf_solve(dwf_ctx ctx, void *x, const void *b, int dagger, double tol, int m
  *         equals sum tr(Q F) / scale.  kind 1 needs the gauge set. */
 int dwf_force(dwf_ctx ctx, double *F, const void *X, const void *Y, int kind, double scale, void *stream);
 
+/* ---- hybrid Monte Carlo molecular dynamics on gauge-shaped fields ---------------
+ * (the step that consumes dwf_force; not treated in the paper).  U, P, X, Y are
+ * canonical FP64 [Lt][Lz][Ly][Lx][4][3][3] device arrays owned by the caller. */
+
+/* U <- exp(i eps P) U for every link, in place; P is meant to be traceless
+ * Hermitian (an su(3) momentum), which is not checked.  exp by scaling and
+ * squaring of a degree-14 Taylor polynomial (FP64 rounding level).
+ * U and P must not alias. */
+int dwf_expi_links(dwf_ctx ctx, double *U, const double *P, double eps, void *stream);
+/* Y = a X + Y over the V*4*9 complex entries. */
+int dwf_gauge_axpy(dwf_ctx ctx, double *Y, double a, const double *X, void *stream);
+/* *result (host) = sum |X_ij|^2 in FP64, i.e. sum_links tr(P^2) for Hermitian P.
+ * Synchronises the stream. */
+int dwf_gauge_norm2(dwf_ctx ctx, double *result, const double *X, void *stream);
+
 /* ---- batched hopping term ---------------------------------------------------- */
 
 /* A plan applies dwf_dhop (same out_parity, dagger and precision) to nrhs[i]

@@ -462,6 +462,32 @@ int dwf_force(dwf_ctx ctx, double *F, const void *X, const void *Y, int kind, do
     return launch_force(ctx, F, X, Y, kind, scale, (hipStream_t)stream);
 }
 
+int dwf_expi_links(dwf_ctx ctx, double *U, const double *P, double eps, void *stream) {
+    CHECK_CTX(ctx);
+    CHECK(U && P, "dwf_expi_links: null pointer");
+    CHECK(U != P, "dwf_expi_links: U and P must not alias");
+    CHECK(std::isfinite(eps), "dwf_expi_links: eps must be finite");
+    return launch_expi_links(ctx->g, U, P, eps, (hipStream_t)stream);
+}
+
+int dwf_gauge_axpy(dwf_ctx ctx, double *Y, double a, const double *X, void *stream) {
+    CHECK_CTX(ctx);
+    CHECK(Y && X, "dwf_gauge_axpy: null pointer");
+    return launch_axpy(Y, a, 0.0, X, ctx->g.vol * 36, DWF_F64, (hipStream_t)stream);
+}
+
+int dwf_gauge_norm2(dwf_ctx ctx, double *result, const double *X, void *stream) {
+    CHECK_CTX(ctx);
+    CHECK(result && X, "dwf_gauge_norm2: null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = launch_reduce(ctx->partials, ctx->scal + 8, X, nullptr, ctx->g.vol * 36, DWF_F64, 0, st);
+    if (rc) return rc;
+    DWF_HIP(hipMemcpyAsync(ctx->host_scal, ctx->scal + 8, sizeof(double), hipMemcpyDeviceToHost, st));
+    DWF_HIP(hipStreamSynchronize(st));
+    *result = ctx->host_scal[0];
+    return DWF_OK;
+}
+
 int dwf_batch_plan(const dwf_ctx *ctxs, int nlat, const int *nrhs, int prec, int dagger, dwf_batch *plan) {
     CHECK(ctxs && nrhs && plan, "dwf_batch_plan: null pointer");
     CHECK(nlat >= 1 && nlat <= 16, "dwf_batch_plan: nlat must be in [1, 16]");

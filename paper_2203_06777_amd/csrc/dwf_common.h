@@ -189,6 +189,9 @@ int launch_cg_residual(dwf_ctx ctx, void *r, int prec_r, const void *w, int prec
 int cg_solve(dwf_ctx ctx, void *x, const void *b, double tol, int maxit, int mode, dwf_cg_stats *stats,
              hipStream_t st);
 
+// HMC link update U <- exp(i eps P) U on canonical gauge fields (hmc.hip).
+int launch_expi_links(const Geom &g, double *U, const double *P, double eps, hipStream_t st);
+
 // Force (force.hip).
 int launch_force(dwf_ctx ctx, double *F, const void *X, const void *Y, int kind, double scale, hipStream_t st);
 

@@ -53,6 +53,9 @@ _SIGS = {
     "dwf_field_bytes": [_P, _I, _I, ctypes.POINTER(ctypes.c_size_t)],
     "dwf_set_gauge": [_P, _P, _P],
     "dwf_set_mobius": [_P, _D, _D],
+    "dwf_expi_links": [_P, _P, _P, _D, _P],
+    "dwf_gauge_axpy": [_P, _P, _D, _P, _P],
+    "dwf_gauge_norm2": [_P, ctypes.POINTER(_D), _P, _P],
     "dwf_get_mobius": [_P, ctypes.POINTER(_D), ctypes.POINTER(_D)],
     "dwf_pack": [_P, _P, _P, _I, _I, _P],
     "dwf_unpack": [_P, _P, _P, _I, _I, _P],
@@ -149,6 +152,20 @@ def dwf_get_mobius(ctx):
     b, c = _D(), _D()
     _check(lib().dwf_get_mobius(ctx, ctypes.byref(b), ctypes.byref(c)))
     return b.value, c.value
+
+
+def dwf_expi_links(ctx, U, P, eps, stream=None):
+    _check(lib().dwf_expi_links(ctx, _ptr(U), _ptr(P), float(eps), _stream(stream)))
+
+
+def dwf_gauge_axpy(ctx, Y, a, X, stream=None):
+    _check(lib().dwf_gauge_axpy(ctx, _ptr(Y), float(a), _ptr(X), _stream(stream)))
+
+
+def dwf_gauge_norm2(ctx, X, stream=None) -> float:
+    r = _D()
+    _check(lib().dwf_gauge_norm2(ctx, ctypes.byref(r), _ptr(X), _stream(stream)))
+    return r.value
 
 
 def dwf_set_gauge(ctx, U, stream=None):
