@@ -396,6 +396,25 @@ def main():
         rows["force_16^4x8"] = {"action_plus_grad_seconds": round(wall, 3), "force_kernel_us": round(ms * 1e3, 1),
                                 "force_kernel_gbs": round(gbs, 1), "force_kernel_frac": round(gbs / HBM_PEAK_GBS, 3)}
         log(f"row force: {rows['force_16^4x8']}")
+
+        # HMC trajectory consuming the force: pseudofermion heatbath, 5 leapfrog steps, Metropolis
+        if row_on("hmc_16^4x8"):
+            from paper_2203_06777_amd import hmc as HM
+
+            rh = {"eps": 0.002, "nsteps": 5, "solver_tol": 1e-10}  # dH = O(1) on these rough random links
+            U0 = U.detach().clone()
+            eta = torch.from_numpy(F.fermion_full(fdims, fls, w["seed_phi"] + 2)).cuda()
+            P0 = torch.from_numpy(F.su3_directions(fdims, w["seed_phi"] + 3)).cuda()
+            phi_h = HM.pseudofermion(op4, U0, eta)
+            for mode, nm in ((0, "fp64_solves"), (2, "mixed_fp16_solves")):
+                Ut = U0.clone()
+                torch.cuda.synchronize()
+                t = time.time()
+                tr = HM.trajectory(op4, Ut, P0.clone(), phi_h, rh["eps"], rh["nsteps"], 0.5, rh["solver_tol"], mode)
+                torch.cuda.synchronize()
+                rh[nm] = {"seconds": round(time.time() - t, 3), "dH": tr["dH"], "accepted": tr["accepted"]}
+            rows["hmc_16^4x8"] = rh
+            log(f"row hmc: {rh}")
         op4.close()
 
     traffic, sha = measured_traffic()
