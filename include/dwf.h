@@ -63,6 +63,7 @@ extern "C" {
 
 typedef struct dwf_ctx_s *dwf_ctx;
 typedef struct dwf_batch_s *dwf_batch;
+typedef struct dwf_dd_s *dwf_dd;
 
 /* Storage precision of an internal field.  F16 and BF16 store spinors and
  * links in 16 bits and compute in FP32. */
@@ -207,6 +208,30 @@ int dwf_gauge_axpy(dwf_ctx ctx, double *Y, double a, const double *X, void *stre
 /* *result (host) = sum |X_ij|^2 in FP64, i.e. sum_links tr(P^2) for Hermitian P.
  * Synchronises the stream. */
 int dwf_gauge_norm2(dwf_ctx ctx, double *result, const double *X, void *stream);
+
+/* ---- domain-decomposed hopping term (t direction) -----------------------------
+ * The communication pattern the paper's library runs between GPUs (face
+ * assembly, halo exchange, interior compute overlapping the exchange), on one
+ * GPU whose t-neighbour domain is itself: the interior is D_h with the
+ * boundary-crossing t-links cut (the hopping kernel on a cut copy of the link
+ * table, on the caller's stream); meanwhile a library stream spin-projects the
+ * boundary slices t = 0 and t = Lt-1 of the input into half-spinor faces
+ * (6 complex per site and s, FP32 for the 16-bit formats) and exchanges them (a
+ * device copy in place of the peer transfer); then the boundary output sites
+ * add link x face.  The result equals dwf_dhop up to the order of the last
+ * addition (within the precision's tolerance). */
+
+/* Plan for precision prec: copies the current link tables with the boundary
+ * t-links cut and allocates four face buffers (2 x 2 x V/(2 Lt) x Ls x 12 reals)
+ * and a stream.  Create it after dwf_set_gauge; re-create after a gauge change. */
+int dwf_dd_create(dwf_ctx ctx, int prec, dwf_dd *dd);
+/* out = D_h^{p<-1-p} in (dagger: D_h^dag) through the decomposition; the
+ * caller's stream orders it like dwf_dhop.  in and out must not alias. */
+int dwf_dd_dhop(dwf_dd dd, void *out, const void *in, int out_parity, int dagger, void *stream);
+/* Face assembly alone (spin projection of the two boundary slices of in into
+ * the plan's send buffers), on the caller's stream: its bandwidth measurement. */
+int dwf_dd_faces(dwf_dd dd, const void *in, int dagger, void *stream);
+int dwf_dd_destroy(dwf_dd dd);
 
 /* ---- batched hopping term ---------------------------------------------------- */
 

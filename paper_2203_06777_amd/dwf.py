@@ -54,6 +54,10 @@ _SIGS = {
     "dwf_set_gauge": [_P, _P, _P],
     "dwf_set_mobius": [_P, _D, _D],
     "dwf_expi_links": [_P, _P, _P, _D, _P],
+    "dwf_dd_create": [_P, _I, ctypes.POINTER(_P)],
+    "dwf_dd_dhop": [_P, _P, _P, _I, _I, _P],
+    "dwf_dd_faces": [_P, _P, _I, _P],
+    "dwf_dd_destroy": [_P],
     "dwf_gauge_axpy": [_P, _P, _D, _P, _P],
     "dwf_gauge_norm2": [_P, ctypes.POINTER(_D), _P, _P],
     "dwf_get_mobius": [_P, ctypes.POINTER(_D), ctypes.POINTER(_D)],
@@ -152,6 +156,24 @@ def dwf_get_mobius(ctx):
     b, c = _D(), _D()
     _check(lib().dwf_get_mobius(ctx, ctypes.byref(b), ctypes.byref(c)))
     return b.value, c.value
+
+
+def dwf_dd_create(ctx, prec):
+    d = _P()
+    _check(lib().dwf_dd_create(ctx, _prec(prec), ctypes.byref(d)))
+    return d
+
+
+def dwf_dd_dhop(dd, out, inp, out_parity, dagger, stream=None):
+    _check(lib().dwf_dd_dhop(dd, _ptr(out), _ptr(inp), int(out_parity), int(dagger), _stream(stream)))
+
+
+def dwf_dd_faces(dd, inp, dagger, stream=None):
+    _check(lib().dwf_dd_faces(dd, _ptr(inp), int(dagger), _stream(stream)))
+
+
+def dwf_dd_destroy(dd):
+    _check(lib().dwf_dd_destroy(dd))
 
 
 def dwf_expi_links(ctx, U, P, eps, stream=None):
