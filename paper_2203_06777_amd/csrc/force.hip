@@ -122,6 +122,7 @@ __device__ inline unsigned visit_site(const ForceArgs &a, unsigned o, unsigned *
 // summed over s in LDS in a fixed order (bitwise reproducible); then nine
 // lanes per link form the nine colour entries of the force.
 constexpr int kForceMaxThreads = 512;
+constexpr int kForceMaxSites = 32;  // ns = max(1, 256 / 8 Ls) <= 32
 
 __global__ void __launch_bounds__(kForceMaxThreads) k_force(const ForceArgs a) {
     extern __shared__ double red[];  // [mu][term][site][s][18]
@@ -135,13 +136,22 @@ __global__ void __launch_bounds__(kForceMaxThreads) k_force(const ForceArgs a) {
     const int s = t - (int)grp * Ls;
     const unsigned sl = grp % ns, mt = grp / ns;
     const int mu = (int)(mt >> 1), term = (int)(mt & 1);
+    // the workgroup's sites: lexicographic index and coordinates, computed once
+    __shared__ unsigned site_tab[kForceMaxSites][5];
+    if ((unsigned)t < ns) {
+        unsigned x[4] = {0, 0, 0, 0}, i = 0;
+        if (lb * ns + t < a.vol) i = visit_site(a, lb * ns + t, x);
+        site_tab[t][0] = i;
+        for (int k = 0; k < 4; ++k) site_tab[t][1 + k] = x[k];
+    }
+    __syncthreads();
     const unsigned o = lb * ns + sl;
     double acc[18];
 #pragma unroll
     for (int k = 0; k < 18; ++k) acc[k] = 0;
     if (o < a.vol) {
-        unsigned x[4];
-        const unsigned i = visit_site(a, o, x);
+        const unsigned i = site_tab[sl][0];
+        const unsigned x[4] = {site_tab[sl][1], site_tab[sl][2], site_tab[sl][3], site_tab[sl][4]};
         const int par = (int)((x[0] + x[1] + x[2] + x[3]) & 1);
         const unsigned xm = mu == 0 ? x[0] : (mu == 1 ? x[1] : (mu == 2 ? x[2] : x[3]));
         const unsigned Lm = mu == 0 ? a.L0 : (mu == 1 ? a.L1 : (mu == 2 ? a.L2 : a.L3));
@@ -184,8 +194,8 @@ __global__ void __launch_bounds__(kForceMaxThreads) k_force(const ForceArgs a) {
         if (eo >= a.vol) continue;
         const double *m = red + (long)((emu * 2) * ns + esl) * Ls * 18;
         const double *n = red + (long)((emu * 2 + 1) * ns + esl) * Ls * 18;
-        unsigned x[4];
-        const unsigned ei = visit_site(a, eo, x);
+        const unsigned ei = site_tab[esl][0];
+        const unsigned x[4] = {site_tab[esl][1], site_tab[esl][2], site_tab[esl][3], site_tab[esl][4]};
         double ore, oim;
         if (a.kind == 0) {  // eta (M^dag + N)
             const double eta = (a.antiperiodic && emu == 3 && x[3] == a.L3 - 1) ? -1.0 : 1.0;
