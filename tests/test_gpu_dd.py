@@ -72,3 +72,29 @@ def test_dd_repeated_calls_and_errors():
     torch.cuda.synchronize()
     D().dwf_dd_destroy(dd)
     op.close()
+
+
+def test_dd_32x32x32x32_ls16_f32_sampled():
+    """The timed shape: the decomposed apply equals dwf_dhop and, on sampled rows (including
+    both boundary slices), the site-wise oracle."""
+    w = F.WORKLOADS["dhop_32^4x16"]
+    dims, ls = w["dims"], w["ls"]
+    op, u = make(dims, ls, w["eps"], w["seed_u"])
+    psi = F.fermion_cb(dims, ls, w["seed_psi"])
+    S = psi.shape[0] // dims[3]
+    rng = np.random.default_rng(1)
+    rows = np.unique(np.concatenate([rng.integers(0, psi.shape[0], 300), rng.integers(0, S, 100),
+                                     rng.integers(psi.shape[0] - S, psi.shape[0], 100)]))
+    pin = op.pack(to_dev(psi), 0, "f32")
+    dd = D().dwf_dd_create(op.handle, "f32")
+    got, want = op.field("f32"), op.field("f32")
+    D().dwf_dd_dhop(dd, got, pin, 1, 0)
+    D().dwf_dhop(op.handle, want, pin, 1, 0, "f32")
+    g = op.unpack(got, 1, "f32")
+    assert rel(g.cpu().numpy(), op.unpack(want, 1, "f32").cpu().numpy()) <= 1e-6
+    sel = g[torch.from_numpy(rows).cuda()].cpu().numpy()
+    assert rel(sel, R.dhop_sites(u, psi, 1, rows)) <= TOL["f32"]
+    D().dwf_dd_destroy(dd)
+    del pin, got, want, g
+    torch.cuda.empty_cache()
+    op.close()
