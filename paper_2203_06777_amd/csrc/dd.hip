@@ -187,12 +187,9 @@ int dd_dhop(dwf_dd d, void *out, const void *in, int out_parity, int dagger, hip
     DWF_HIP(hipMemcpyAsync(d->recv[1], d->send[1], d->face_bytes, hipMemcpyDeviceToDevice, d->comm));
     DWF_HIP(hipEventRecord(d->halo, d->comm));
     // interior on the caller's stream with the cut links, overlapping the faces
-    void *saved = ctx->links[d->prec][out_parity];
-    ctx->links[d->prec][out_parity] = d->cut[out_parity];
     DhopCall c{in, out, nullptr, out_parity, dagger, EPI_SCALE, 1.0, 0.0, d->prec, d->prec};
-    rc = launch_dhop(ctx, c, ctx->shape[d->prec][dagger], st);
-    ctx->links[d->prec][out_parity] = saved;
-    if (rc) return rc;
+    c.links = d->cut[out_parity];
+    if ((rc = launch_dhop(ctx, c, ctx->shape[d->prec][dagger], st))) return rc;
     DWF_HIP(hipStreamWaitEvent(st, d->halo, 0));
     return dd_faces_any(d, (char *)out, nullptr, dagger, 1 + out_parity, st);
 }

@@ -257,6 +257,7 @@ int launch_dhop(dwf_ctx ctx, const DhopCall &c, const DhopShape &shape_in, hipSt
     a.cg_alpha = c.cg_alpha;
     a.cg_live = c.cg_live;
     if (c.schur_coef) m5inv_coefficients(g, a.coef, true);
+    if (c.links) a.links = (const char *)c.links;
     if (c.epi == EPI_CG && (!c.norm_out || !c.cg_alpha || !c.cg_live || !c.z))
         return fail(DWF_EINVAL, "hopping kernel: CG epilogue needs z, partials and the solver scalars");
     int threads;

@@ -101,6 +101,7 @@ struct DhopCall {
     long *nparts_out = nullptr;  // receives the number of partials written
     const double *cg_alpha = nullptr, *cg_live = nullptr;  // EPI_CG: device scalars of the solver
     bool schur_coef = false;     // EPI_M5INV: apply Mooee^-1 (b + c K) (identical to Mooee^-1 for Shamir)
+    const void *links = nullptr; // gathered link table to use instead of the context's (same layout)
 };
 
 // Solver workspace (allocated on first solve).

@@ -89,3 +89,25 @@ def test_null_context_is_an_error():
     assert l.dwf_batch_launch(None, None) == -1
     assert l.dwf_batch_free(None) == 0
     assert l.dwf_destroy(None) == 0
+
+
+def test_null_handles_of_the_extensions_are_errors():
+    """Moebius, HMC and domain-decomposition entry points reject null handles without a device."""
+    l = lib()
+    l.dwf_set_mobius.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double]
+    assert l.dwf_set_mobius(None, 1.5, 0.5) == -1
+    assert b"null context" in l.dwf_last_error()
+    b, c = ctypes.c_double(), ctypes.c_double()
+    assert l.dwf_get_mobius(None, ctypes.byref(b), ctypes.byref(c)) == -1
+    l.dwf_expi_links.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]
+    assert l.dwf_expi_links(None, None, None, 0.1, None) == -1
+    l.dwf_gauge_axpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
+    assert l.dwf_gauge_axpy(None, None, 1.0, None, None) == -1
+    r = ctypes.c_double()
+    assert l.dwf_gauge_norm2(None, ctypes.byref(r), None, None) == -1
+    d = ctypes.c_void_p()
+    assert l.dwf_dd_create(None, 1, ctypes.byref(d)) == -1
+    assert l.dwf_dd_dhop(None, None, None, 0, 0, None) == -1
+    assert b"null plan" in l.dwf_last_error()
+    assert l.dwf_dd_faces(None, None, 0, None) == -1
+    assert l.dwf_dd_destroy(None) == 0
