@@ -474,7 +474,7 @@ def main():
         "frac_of_copy": round(achieved / copy_gbs, 4),
         "cpu_baseline": cpu,
         # the paper's own figures, on other hardware and an unstated workload: context, not the target
-        "paper_context": {"dwf_tflops_per_gpu": 1.3, "hardware": "AMD MI100 (HIP port, not fully optimised)",
+        "paper_context": {"dwf_tflops_per_gpu": 1.3, "hardware": "AMD MI100 (early HIP port)",
                           "dwf_kernels_hbm_frac": 0.8, "hardware_bw": "NVIDIA A100",
                           "note": "no lattice size, Ls, precision or byte model stated"},
         "rows": rows,
