@@ -6,7 +6,10 @@ import torch
 
 from synth import fields as F
 
-TOL = {"f64": 1e-13, "f32": 1e-6, "f16": 5e-3, "bf16": 2e-2}
+# rel-L2 per operator application against the FP64 oracle.  16-bit storage (FP16 and BF16) is
+# held to 5e-3; measured on every configuration the tests use: FP16 <= 4.4e-4, BF16 <= 3.4e-3
+# (the Moebius M_pc^dag M_pc, with four rounded intermediates, is the largest).
+TOL = {"f64": 1e-13, "f32": 1e-6, "f16": 5e-3, "bf16": 5e-3}
 
 
 def rel(a, b):

@@ -116,19 +116,40 @@ def test_full_solve(dagger, mode):
         assert rel(got, want) <= 1e-9
 
 
-def test_cg_24x24x24x24_mixed_agrees_with_fp64():
-    """The CG workload shape: both solvers reach 1e-10 and agree to 1e-8; the oracle checks the residual."""
+@pytest.fixture(scope="module")
+def cg_workload():
+    """The CG workload (24^4 x 12, eps 0.3, tol 1e-10): context, source, and the FP64 solution."""
     w = F.WORKLOADS["cg_24^4x12"]
     dims, ls = w["dims"], w["ls"]
     op, u = make(dims, ls, w["eps"], w["seed_u"], w["M5"], w["mf"])
     b = F.fermion_cb(dims, ls, w["seed_psi"])
     bi = op.pack(to_dev(b), 1, "f64")
-    xs = {}
-    for mode in (0, 2):
-        x = op.zeros("f64")
-        st = D().dwf_cg(op.handle, x, bi, w["tol"], 20000, mode)
-        assert st["true_rel_resid"] <= w["tol"]
-        xs[mode] = op.unpack(x, 1, "f64").cpu().numpy()
-    assert rel(xs[2], xs[0]) <= 1e-8
-    r = b - C.mdagm(u, xs[0], w["M5"], w["mf"])
+    x = op.zeros("f64")
+    st = D().dwf_cg(op.handle, x, bi, w["tol"], 20000, 0)
+    assert st["true_rel_resid"] <= w["tol"]
+    x64 = op.unpack(x, 1, "f64").cpu().numpy()
+    yield w, op, u, b, bi, x64
+    op.close()
+    torch.cuda.empty_cache()
+
+
+def test_cg_24x24x24x24_fp64_residual_by_oracle(cg_workload):
+    """The FP64 solver's solution, its residual recomputed by the C oracle."""
+    w, op, u, b, bi, x64 = cg_workload
+    r = b - C.mdagm(u, x64, w["M5"], w["mf"])
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 2e-10
+
+
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_cg_24x24x24x24_mixed_agrees_with_fp64(cg_workload, mode):
+    """The CG workload, defect correction with FP32 / FP16 / BF16 inner solves: the true residual
+    reaches 1e-10 (recomputed by the oracle) and the solution agrees with FP64 CG to 1e-8."""
+    w, op, u, b, bi, x64 = cg_workload
+    x = op.zeros("f64")
+    st = D().dwf_cg(op.handle, x, bi, w["tol"], 20000, mode)
+    assert st["true_rel_resid"] <= w["tol"]
+    assert st["outer_iters"] >= 2
+    got = op.unpack(x, 1, "f64").cpu().numpy()
+    assert rel(got, x64) <= 1e-8
+    r = b - C.mdagm(u, got, w["M5"], w["mf"])
     assert np.linalg.norm(r) / np.linalg.norm(b) <= 2e-10
