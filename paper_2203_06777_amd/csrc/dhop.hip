@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(kMaxDhopThreads) k_dhop(const DhopArgs a) {
 #pragma unroll
             for (int k = 0; k < 24; ++k) acc[k] += beta * zv[k];
         }
-        m5inv_lds<DAG>(a, Ls, lds, j, s, acc);
+        m5inv_lds<DAG>(a.m5i, Ls, lds, j, s, acc);
         if (!active) return;
     }
     store_spinor_off<PO>(a.out, spinor_off<PO, Off>(c, Ls, s), Ls * 16, acc, a.nt_store != 0);
@@ -133,24 +133,25 @@ DhopShape default_shape(const Geom &g) {
 }
 
 // Mooee = d - e K:  Mooee^-1 = sum_n coef[n] K^n with coef[n] = q^-(n+1) / (e (1 + mf q^-Ls)),
-// q = d / e.  The Schur factor Mooee^-1 (b + c K) = -(c/e) + (b + c d/e) Mooee^-1 (b + c K
-// differs from Mooee by a multiple of the identity), so only its coefficients change.  For
-// Shamir (e = 1, b = 1, c = 0) both tables are the plain M5op^-1 one, bit for bit.
-void m5inv_coefficients(const Geom &g, double *coef, bool schur) {
-    const double e = mooee_e(g), d = mooee_d(g) / e;
+// q = d / e, and the recurrence factors 1/d, e/d.  The Moebius Schur factor
+// Mooee^-1 (b + c K) = -(c/e) + (b + c q) Mooee^-1 (b + c K differs from Mooee by a multiple of
+// the identity) is applied as y -> f y + g v after the inverse.
+void m5inv_setup(const Geom &g, M5InvCoef &m, bool schur) {
+    const double d = mooee_d(g), e = mooee_e(g), q = d / e;
     double dn = 1.0;
-    for (int n = 0; n < g.Ls; ++n) dn /= d;  // d^-Ls
+    for (int n = 0; n < g.Ls; ++n) dn /= q;  // q^-Ls
     const double norm = 1.0 / (1.0 + g.mf * dn) / e;
-    double p = 1.0 / d;
+    double p = 1.0 / q;
     for (int n = 0; n < kMaxLs; ++n) {
-        coef[n] = n < g.Ls ? p * norm : 0.0;
-        p /= d;
+        m.coef[n] = n < g.Ls ? p * norm : 0.0;
+        p /= q;
     }
-    if (schur && g.mobius) {
-        const double f = g.b5 + g.c5 * d;
-        for (int n = 0; n < g.Ls; ++n) coef[n] *= f;
-        coef[0] -= g.c5 / e;
-    }
+    m.mf = g.mf;
+    m.id = 1.0 / d;
+    m.ed = e / d;
+    m.schur = schur && g.mobius ? 1 : 0;
+    m.f = m.schur ? g.b5 + g.c5 * q : 1.0;
+    m.g = m.schur ? -g.c5 / e : 0.0;
 }
 
 template <int PI, int PO, int DAG, int EPI>
@@ -220,7 +221,7 @@ bool fill_dhop_args(dwf_ctx ctx, const DhopShape &shape, int prec_in, int out_pa
     a.d5 = mooee_d(g);
     a.e5 = mooee_e(g);
     a.mf = g.mf;
-    m5inv_coefficients(g, a.coef);
+    m5inv_setup(g, a.m5i, false);
     const bool rows_mode = shape.rows > 0 && row_shape_ok(g, shape, prec_in, ctx->lds_limit);
     a.rows = rows_mode ? shape.rows : 0;
     a.nrows = (unsigned)(g.vol / g.L[0]);
@@ -256,7 +257,7 @@ int launch_dhop(dwf_ctx ctx, const DhopCall &c, const DhopShape &shape_in, hipSt
     a.norm_out = (c.epi == EPI_M5 || c.epi == EPI_CG) ? c.norm_out : nullptr;
     a.cg_alpha = c.cg_alpha;
     a.cg_live = c.cg_live;
-    if (c.schur_coef) m5inv_coefficients(g, a.coef, true);
+    if (c.schur_coef) m5inv_setup(g, a.m5i, true);
     if (c.links) a.links = (const char *)c.links;
     if (c.epi == EPI_CG && (!c.norm_out || !c.cg_alpha || !c.cg_live || !c.z))
         return fail(DWF_EINVAL, "hopping kernel: CG epilogue needs z, partials and the solver scalars");

@@ -166,8 +166,6 @@ int launch_m5(const Geom &g, void *out, const void *in, int dagger, int inverse,
 // out = (d x + db z) - K (e x + eb z)  (K^dag when dagger; z optional, out may alias z).
 int launch_m5_op(const Geom &g, void *out, const void *x, double d, double e, const void *z, double db, double eb,
                  int dagger, long nsites, int prec, hipStream_t st);
-// Coefficients of Mooee^-1 = sum_n coef[n] K^n; with schur, of Mooee^-1 (b + c K).
-void m5inv_coefficients(const Geom &g, double *coef, bool schur = false);
 
 // BLAS-1 and reductions (blas.hip). n = number of complex elements.
 int launch_reduce(double *partials, double *dst, const void *x, const void *y, long n, int prec, int dot,

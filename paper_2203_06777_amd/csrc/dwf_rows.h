@@ -16,6 +16,7 @@
 #include <type_traits>
 
 #include "dwf_dhop_core.h"
+#include "dwf_m5inv.h"
 
 namespace dwf {
 
@@ -35,7 +36,7 @@ struct DhopArgs {
     double alpha, beta, d5, e5, mf;  // Mooee = d5 - e5 K
     double *norm_out;
     const double *cg_alpha, *cg_live;
-    double coef[kMaxLs];
+    M5InvCoef m5i;  // EPI_M5INV: Mooee^-1 (or the Moebius Schur factor)
 };
 
 // Host side: fills the geometry, launch-shape and link fields of a for one output
@@ -75,39 +76,6 @@ __device__ __forceinline__ void block_norm_partial(double *partials, const A *v,
         __syncthreads();
     }
     if (t == 0) partials[blockIdx.x] = red[0];
-}
-
-// Apply M5op^-1 (DAG: M5op^-dag) to the Ls-vector v held by the site's lanes,
-// through LDS.  Lower spins (2,3) couple s to s+n, upper spins (0,1) to s-n
-// (swapped for the adjoint); coef[n] = d^-(n+1) / (1 + mf d^-Ls).
-template <int DAG, typename A>
-__device__ __forceinline__ void m5inv_lds(const DhopArgs &a, int Ls, A *lds, int j, int s, A *v) {
-    A *mine = lds + (j * Ls + s) * 25;
-#pragma unroll
-    for (int k = 0; k < 24; ++k) mine[k] = v[k];
-    __syncthreads();
-    A o[24];
-#pragma unroll
-    for (int k = 0; k < 24; ++k) o[k] = 0;
-    const A *site = lds + j * Ls * 25;
-    for (int n = 0; n < Ls; ++n) {
-        const A cf = (A)a.coef[n];
-        int sp = s + n;
-        const A fp = sp < Ls ? cf : (A)(-a.mf) * cf;
-        sp = sp < Ls ? sp : sp - Ls;
-        int sm = s - n;
-        const A fm = sm >= 0 ? cf : (A)(-a.mf) * cf;
-        sm = sm >= 0 ? sm : sm + Ls;
-        const A *vu = site + (DAG ? sp : sm) * 25;  // upper spins
-        const A *vl = site + (DAG ? sm : sp) * 25;  // lower spins
-        const A fu = DAG ? fp : fm, fl = DAG ? fm : fp;
-#pragma unroll
-        for (int k = 0; k < 12; ++k) o[k] = fma_(fu, vu[k], o[k]);
-#pragma unroll
-        for (int k = 12; k < 24; ++k) o[k] = fma_(fl, vl[k], o[k]);
-    }
-#pragma unroll
-    for (int k = 0; k < 24; ++k) v[k] = o[k];
 }
 
 // acc = M5op z + alpha acc at lane (c, s) (adjoint: P_+ <-> P_-), zoff = offset of z(c, s):
@@ -384,7 +352,7 @@ __device__ __forceinline__ void row_block(const DhopArgs &a, unsigned q0, const 
             for (int k = 0; k < 24; ++k) acc[k] += beta * zv[k];
         }
         __syncthreads();
-        m5inv_lds<DAG>(a, Ls, lds, r * L0h + xh, s, acc);
+        m5inv_lds<DAG>(a.m5i, Ls, lds, r * L0h + xh, s, acc);
         if (!active) return;
     }
     store_spinor_off<PO>(out_f, spinor_off<PO, Off>(c, Ls, s), Ls * 16, acc, a.nt_store != 0);

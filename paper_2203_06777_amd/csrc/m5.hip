@@ -5,10 +5,10 @@
 // One lane per (4D site, s); the Ls lanes of a site exchange their spinors
 // through LDS, so the kernel reads and writes each field once and out may
 // alias an input.  K couples s to s +- 1 (P_- to s+1, P_+ to s-1, with -mf on
-// the wraps); the inverse is, per chirality, the geometric series of the
-// twisted shift K (K^Ls = -mf):
-//   (d - e K)^-1 = (1/e) sum_n q^-(n+1) K^n / (1 + mf q^-Ls),  q = d / e.
+// the wraps); the inverse solves, per chirality and component, the first-order
+// recurrence along s closed at the wall (dwf_m5inv.h).
 #include "dwf_device.h"
+#include "dwf_m5inv.h"
 
 namespace dwf {
 
@@ -18,8 +18,14 @@ struct M5Args {
     long nsites;
     int Ls, spb, dagger, inverse;
     double d, e, db, eb, mf;
-    double coef[kMaxLs];
+    M5InvCoef m5i;
 };
+
+template <typename A>
+__device__ __forceinline__ void m5inv_lds_dyn(const M5Args &a, int Ls, A *lds, int j, int s, A *v) {
+    if (a.dagger) m5inv_lds<1>(a.m5i, Ls, lds, j, s, v);
+    else m5inv_lds<0>(a.m5i, Ls, lds, j, s, v);
+}
 
 template <int P>
 __global__ void __launch_bounds__(1024) k_m5(const M5Args a) {
@@ -59,6 +65,12 @@ __global__ void __launch_bounds__(1024) k_m5(const M5Args a) {
             }
         }
     }
+    if (a.inverse) {  // every lane of the workgroup takes part (two barriers)
+        m5inv_lds_dyn(a, Ls, lds, j, s, w);
+        if (!active) return;
+        store_spinor<P>(a.out, c, Ls, s, w);
+        return;
+    }
     A *mine = lds + (j * Ls + s) * 25;
 #pragma unroll
     for (int k = 0; k < 24; ++k) mine[k] = w[k];
@@ -67,35 +79,14 @@ __global__ void __launch_bounds__(1024) k_m5(const M5Args a) {
     const A *site = lds + j * Ls * 25;
     const A mf = (A)a.mf;
     A o[24];
-    if (!a.inverse) {
-        const int su = s + 1 < Ls ? s + 1 : 0, sd = s >= 1 ? s - 1 : Ls - 1;
-        const A fu = s + 1 < Ls ? (A)1 : -mf, fd = s >= 1 ? (A)1 : -mf;
-        const A *zu = site + su * 25, *zd = site + sd * 25;
-        // upper spins: P_+ takes s-1 (adjoint: s+1); lower spins: P_- takes s+1 (adjoint: s-1)
+    const int su = s + 1 < Ls ? s + 1 : 0, sd = s >= 1 ? s - 1 : Ls - 1;
+    const A fu = s + 1 < Ls ? (A)1 : -mf, fd = s >= 1 ? (A)1 : -mf;
+    const A *zu = site + su * 25, *zd = site + sd * 25;
+    // upper spins: P_+ takes s-1 (adjoint: s+1); lower spins: P_- takes s+1 (adjoint: s-1)
 #pragma unroll
-        for (int k = 0; k < 12; ++k) o[k] = v[k] - (a.dagger ? fu * zu[k] : fd * zd[k]);
+    for (int k = 0; k < 12; ++k) o[k] = v[k] - (a.dagger ? fu * zu[k] : fd * zd[k]);
 #pragma unroll
-        for (int k = 12; k < 24; ++k) o[k] = v[k] - (a.dagger ? fd * zd[k] : fu * zu[k]);
-    } else {
-#pragma unroll
-        for (int k = 0; k < 24; ++k) o[k] = 0;
-        for (int n = 0; n < Ls; ++n) {
-            const A cf = (A)a.coef[n];
-            int sp = s + n;
-            const A fp = sp < Ls ? cf : -mf * cf;
-            sp = sp < Ls ? sp : sp - Ls;
-            int sm = s - n;
-            const A fm = sm >= 0 ? cf : -mf * cf;
-            sm = sm >= 0 ? sm : sm + Ls;
-            const A *vu = site + (a.dagger ? sp : sm) * 25;
-            const A *vl = site + (a.dagger ? sm : sp) * 25;
-            const A fu = a.dagger ? fp : fm, fl = a.dagger ? fm : fp;
-#pragma unroll
-            for (int k = 0; k < 12; ++k) o[k] += fu * vu[k];
-#pragma unroll
-            for (int k = 12; k < 24; ++k) o[k] += fl * vl[k];
-        }
-    }
+    for (int k = 12; k < 24; ++k) o[k] = v[k] - (a.dagger ? fd * zd[k] : fu * zu[k]);
     store_spinor<P>(a.out, c, Ls, s, o);
 }
 
@@ -129,7 +120,7 @@ int launch_m5(const Geom &g, void *out, const void *in, int dagger, int inverse,
     a.d = mooee_d(g);
     a.e = mooee_e(g);
     a.db = a.eb = 0.0;
-    m5inv_coefficients(g, a.coef);
+    m5inv_setup(g, a.m5i, false);
     return launch_m5_args(g, a, nsites, prec, st);
 }
 
@@ -145,7 +136,7 @@ int launch_m5_op(const Geom &g, void *out, const void *x, double d, double e, co
     a.e = e;
     a.db = db;
     a.eb = eb;
-    for (int n = 0; n < kMaxLs; ++n) a.coef[n] = 0.0;
+    m5inv_setup(g, a.m5i, false);
     return launch_m5_args(g, a, nsites, prec, st);
 }
 
