@@ -159,6 +159,17 @@ int dwf_dw(dwf_ctx ctx, void *out, const void *in, int dagger, int prec, void *s
 int dwf_norm2(dwf_ctx ctx, double *result, const void *x, int full, int prec, void *stream);
 /* result[0] + i result[1] (host) = <x, y> = sum conj(x) y in FP64. Synchronises. */
 int dwf_cdot(dwf_ctx ctx, double *result, const void *x, const void *y, int full, int prec, void *stream);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): result[0] + i result[1] = <x, y> as
+ * dwf_cdot computes it (y != NULL), or result[0] = |x|^2, result[1] = 0 as dwf_norm2 does
+ * (y == NULL), bit for bit, written to caller-owned DEVICE memory (2 doubles).  Enqueued on
+ * the stream; no synchronisation, no allocation, no memset (the call can be captured in a
+ * graph).  The per-workgroup partial sums live in one static 16 KiB device array per GPU
+ * (set up by dwf_create, held until the process ends) instead of the context's buffer, so
+ * calls that overlap on one GPU (other streams or host threads) race on it and must be
+ * ordered by the caller.  The array holds the partials of the fixed reduction grid for any
+ * field size; a build whose grid did not fit would reject the call with DWF_EINVAL. */
+int dwf_cdot_noalloc(dwf_ctx ctx, double *result, const void *x, const void *y, int full, int prec, void *stream);
 /* y = (a_re + i a_im) x + y. */
 int dwf_axpy(dwf_ctx ctx, void *y, double a_re, double a_im, const void *x, int full, int prec, void *stream);
 

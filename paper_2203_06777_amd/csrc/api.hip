@@ -139,6 +139,11 @@ int dwf_create(const dwf_geom *geom, dwf_ctx *out) {
         return fail(code, msg);
     };
     if (hipGetDevice(&c->device) != hipSuccess) return cleanup(DWF_EHIP, "dwf_create: no HIP device");
+    if (int rc = noalloc_setup(c->device)) {
+        const std::string msg = dwf_last_error();
+        dwf_destroy(c);
+        return fail(rc, msg);
+    }
     {
         int lds = 0;
         if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) == hipSuccess && lds > 0)

@@ -181,6 +181,10 @@ int op_mdagm(dwf_ctx ctx, void *out, const void *in, int prec, void *tmp_o, hipS
 int op_mpcdag_cg(dwf_ctx ctx, void *r, int prec_r, const void *y, int prec, const double *cg_alpha,
                  const double *cg_live, double *partials, long *nparts, hipStream_t st);
 
+// Static reduction scratch of the no-allocation entry point (noalloc.hip): resolves its
+// device address on `device`, which must be current; once per device, thread-safe.
+int noalloc_setup(int device);
+
 // Solvers (solver.hip).
 // r (prec_r) -= (*cg_alpha) w (prec_w) when *cg_live != 0, with |r|^2 partials (count in *nparts).
 int launch_cg_residual(dwf_ctx ctx, void *r, int prec_r, const void *w, int prec_w, const double *cg_alpha,

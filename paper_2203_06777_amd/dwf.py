@@ -71,6 +71,7 @@ _SIGS = {
     "dwf_dw": [_P, _P, _P, _I, _I, _P],
     "dwf_norm2": [_P, ctypes.POINTER(_D), _P, _I, _I, _P],
     "dwf_cdot": [_P, ctypes.POINTER(_D), _P, _P, _I, _I, _P],
+    "dwf_cdot_noalloc": [_P, _P, _P, _P, _I, _I, _P],
     "dwf_axpy": [_P, _P, _D, _D, _P, _I, _I, _P],
     "dwf_cg": [_P, _P, _P, _D, _I, _I, ctypes.POINTER(dwf_cg_stats), _P],
     "dwf_cg_set_inner": [_P, _D, _I],
@@ -238,6 +239,14 @@ def dwf_cdot(ctx, x, y, full, prec, stream=None) -> complex:
     r = (_D * 2)()
     _check(lib().dwf_cdot(ctx, r, _ptr(x), _ptr(y), int(full), _prec(prec), _stream(stream)))
     return complex(r[0], r[1])
+
+
+def dwf_cdot_noalloc(ctx, result, x, y, full, prec, stream=None):
+    """<x, y> (y given) or |x|^2 (y None) into result[0], result[1] (a device FP64 tensor of >= 2
+    elements); enqueued on the stream, no synchronisation, no allocation."""
+    if result.dtype != torch.float64 or result.numel() < 2 or not result.is_cuda:
+        raise ValueError("dwf_cdot_noalloc: result must be a device float64 tensor of >= 2 elements")
+    _check(lib().dwf_cdot_noalloc(ctx, _ptr(result), _ptr(x), _ptr(y), int(full), _prec(prec), _stream(stream)))
 
 
 def dwf_axpy(ctx, y, a, x, full, prec, stream=None):

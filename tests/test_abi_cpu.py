@@ -89,6 +89,9 @@ def test_null_context_is_an_error():
     assert l.dwf_batch_launch(None, None) == -1
     assert l.dwf_batch_free(None) == 0
     assert l.dwf_destroy(None) == 0
+    l.dwf_cdot_noalloc.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    assert l.dwf_cdot_noalloc(None, None, None, None, 0, 1, None) == -1
+    assert b"null context" in l.dwf_last_error()
 
 
 def test_null_handles_of_the_extensions_are_errors():
