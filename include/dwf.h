@@ -220,28 +220,34 @@ int dwf_gauge_axpy(dwf_ctx ctx, double *Y, double a, const double *X, void *stre
  * Synchronises the stream. */
 int dwf_gauge_norm2(dwf_ctx ctx, double *result, const double *X, void *stream);
 
-/* ---- domain-decomposed hopping term (t direction) -----------------------------
- * The communication pattern the paper's library runs between GPUs (face
- * assembly, halo exchange, interior compute overlapping the exchange), on one
- * GPU whose t-neighbour domain is itself: the interior is D_h with the
- * boundary-crossing t-links cut (the hopping kernel on a cut copy of the link
- * table, on the caller's stream); meanwhile a library stream spin-projects the
- * boundary slices t = 0 and t = Lt-1 of the input into half-spinor faces
- * (6 complex per site and s, FP32 for the 16-bit formats) and exchanges them (a
- * device copy in place of the peer transfer); then the boundary output sites
- * add link x face.  The result equals dwf_dhop up to the order of the last
- * addition (within the precision's tolerance). */
+/* ---- domain-decomposed hopping term ------------------------------------------------
+ * The communication pattern the paper's library runs between GPUs (its performance
+ * section: face assembly and halo exchange overlapped with the interior computation, all
+ * DWF kernels including face assembly near the memory-bandwidth peak), on one GPU whose
+ * neighbour domain across every cut direction is itself.  A plan cuts a set of directions
+ * (DWF_CUT_X | DWF_CUT_Y | DWF_CUT_Z | DWF_CUT_T; x, y and z is the 2x2x2x1 split over eight
+ * GPUs).  An output site is on the boundary when a hop crosses a cut.  dwf_dd_dhop runs, on
+ * a stream of the plan, one face kernel (the half spinors, 6 complex per site and s in the
+ * arithmetic type, of the input slices x_mu = 0 and x_mu = L_mu - 1 of every cut mu, with the
+ * projector of the hop that crosses), one device copy standing in for the peer transfers, and
+ * the boundary sites computed from the received faces; meanwhile the caller's stream runs the
+ * hopping kernel on the interior sites only.  The result equals dwf_dhop bit for bit. */
+#define DWF_CUT_X 1
+#define DWF_CUT_Y 2
+#define DWF_CUT_Z 4
+#define DWF_CUT_T 8
 
-/* Plan for precision prec: copies the current link tables with the boundary
- * t-links cut and allocates four face buffers (2 x 2 x V/(2 Lt) x Ls x 12 reals)
- * and a stream.  Create it after dwf_set_gauge; re-create after a gauge change. */
-int dwf_dd_create(dwf_ctx ctx, int prec, dwf_dd *dd);
-/* out = D_h^{p<-1-p} in (dagger: D_h^dag) through the decomposition; the
- * caller's stream orders it like dwf_dhop.  in and out must not alias. */
+/* Plan for precision prec and the cut mask `cuts` (1..15): allocates the send and receive
+ * face buffers (2 x sum over cut mu of V/(2 L_mu) x Ls x 12 reals each), the boundary site
+ * lists and a stream.  The plan reads the context's link tables at every apply (a gauge
+ * change needs no new plan); the context must outlive the plan. */
+int dwf_dd_create(dwf_ctx ctx, int prec, int cuts, dwf_dd *dd);
+/* out = D_h^{p<-1-p} in (dagger: D_h^dag) through the decomposition; the caller's stream
+ * orders it like dwf_dhop.  in and out must not alias. */
 int dwf_dd_dhop(dwf_dd dd, void *out, const void *in, int out_parity, int dagger, void *stream);
-/* Face assembly alone (spin projection of the two boundary slices of in into
- * the plan's send buffers), on the caller's stream: its bandwidth measurement. */
-int dwf_dd_faces(dwf_dd dd, const void *in, int dagger, void *stream);
+/* Face assembly alone (every cut face of in for output parity out_parity, into the plan's
+ * send buffer), on the caller's stream: its bandwidth measurement. */
+int dwf_dd_faces(dwf_dd dd, const void *in, int out_parity, int dagger, void *stream);
 int dwf_dd_destroy(dwf_dd dd);
 
 /* ---- batched hopping term ---------------------------------------------------- */

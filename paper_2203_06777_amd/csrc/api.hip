@@ -32,9 +32,9 @@ int batch_plan(const dwf_ctx *ctxs, int nlat, const int *nrhs, int prec, int dag
 int batch_capture(dwf_batch p, void *const *outs, const void *const *ins, int out_parity, hipStream_t st);
 int batch_launch(dwf_batch p, hipStream_t st);
 int batch_free(dwf_batch p);
-int dd_create(dwf_ctx ctx, int prec, dwf_dd *out);
+int dd_create(dwf_ctx ctx, int prec, unsigned cut, dwf_dd *out);
 int dd_dhop(dwf_dd d, void *out, const void *in, int out_parity, int dagger, hipStream_t st);
-int dd_face_only(dwf_dd d, const void *in, int dagger, hipStream_t st);
+int dd_face_only(dwf_dd d, const void *in, int out_parity, int dagger, hipStream_t st);
 int dd_destroy(dwf_dd d);
 
 static bool valid_prec(int p) { return p >= DWF_F64 && p <= DWF_BF16; }
@@ -497,13 +497,14 @@ int dwf_gauge_norm2(dwf_ctx ctx, double *result, const double *X, void *stream) 
     return DWF_OK;
 }
 
-int dwf_dd_create(dwf_ctx ctx, int prec, dwf_dd *dd) {
+int dwf_dd_create(dwf_ctx ctx, int prec, int cuts, dwf_dd *dd) {
     CHECK_CTX(ctx);
-    CHECK_GAUGE(ctx);
     CHECK(dd != nullptr, "dwf_dd_create: null output");
     CHECK(valid_prec(prec), "dwf_dd_create: bad precision");
+    CHECK(cuts >= 1 && cuts <= 15, "dwf_dd_create: cuts must be a nonzero mask of DWF_CUT_X|Y|Z|T");
+    CHECK(ctx->g.half <= 0xffffffffL, "dwf_dd_create: more than 2^32 checkerboard sites");
     *dd = nullptr;
-    return dd_create(ctx, prec, dd);
+    return dd_create(ctx, prec, (unsigned)cuts, dd);
 }
 
 int dwf_dd_dhop(dwf_dd dd, void *out, const void *in, int out_parity, int dagger, void *stream) {
@@ -514,10 +515,11 @@ int dwf_dd_dhop(dwf_dd dd, void *out, const void *in, int out_parity, int dagger
     return dd_dhop(dd, out, in, out_parity, dagger, (hipStream_t)stream);
 }
 
-int dwf_dd_faces(dwf_dd dd, const void *in, int dagger, void *stream) {
+int dwf_dd_faces(dwf_dd dd, const void *in, int out_parity, int dagger, void *stream) {
     CHECK(dd != nullptr && in != nullptr, "dwf_dd_faces: null pointer");
+    CHECK(out_parity == 0 || out_parity == 1, "dwf_dd_faces: out_parity must be 0 or 1");
     CHECK(dagger == 0 || dagger == 1, "dwf_dd_faces: dagger must be 0 or 1");
-    return dd_face_only(dd, in, dagger, (hipStream_t)stream);
+    return dd_face_only(dd, in, out_parity, dagger, (hipStream_t)stream);
 }
 
 int dwf_dd_destroy(dwf_dd dd) { return dd_destroy(dd); }

@@ -1,73 +1,177 @@
-// Domain-decomposed hopping term along t, the communication pattern the
-// paper's library uses between GPUs (its face assembly and halo exchange),
-// on one GPU: the lattice is one domain whose t-neighbour domain is itself.
+// Domain-decomposed hopping term, the communication pattern the paper's library runs between
+// GPUs (face assembly, halo exchange, interior compute overlapping the exchange), on one GPU
+// whose neighbour domain across every cut direction is itself.
 //
-//   interior  D_h with the t-links that cross the domain boundary set to zero
-//             (the unchanged hopping kernel on a cut copy of the link table); it
-//             needs no halo and runs on the caller's stream;
-//   faces     meanwhile, on a second stream: the boundary slices of the input
-//             (t = 0 for the forward hops of t = Lt-1, t = Lt-1 for the
-//             backward hops of t = 0) are spin-projected to half spinors
-//             (6 complex per site and s) and exchanged (a device copy stands in
-//             for the peer transfer: the neighbour domain is this one);
-//   exterior  after both, the boundary output sites add link x received half
-//             spinor, reconstructed, with the links of the doubled (gathered)
-//             table the receiving domain owns.
-// Interior + exterior equals D_h up to the order of the last addition.
+// A plan cuts any set of the four directions (the decomposition 2x2x2x1 of eight GPUs cuts x, y
+// and z; each GPU then holds this lattice as its domain).  An output site is on the boundary
+// when one of its hops crosses a cut (coordinate 0 or L_mu - 1 along a cut mu).
+//
+//   faces     one kernel spin-projects every face the neighbour domains need into one send
+//             buffer: per cut mu, the input slice x_mu = 0 with the forward-hop projector and
+//             the slice x_mu = L_mu - 1 with the backward-hop one, half spinors of 6 complex per
+//             site and s in the arithmetic type.  The x faces live in the halved-x checkerboard
+//             layout: the slice x = 0 of one parity holds site xh = 0 of every other row.
+//   exchange  one device copy of the send buffer into the receive buffer (the stand-in for the
+//             peer transfers: every face comes back to this domain).
+//   interior  the hopping kernel writing only the output sites with no hop across a cut (a
+//             workgroup whose rows all lie on a y, z or t cut leaves at once), on the caller's
+//             stream, overlapping the faces and the exchange on the plan's stream.
+//   exterior  after the exchange, one lane per (boundary site, s) computes the whole stencil of
+//             its site, hops across a cut from the received half spinors and the rest from the
+//             local input, and writes the site (no read-modify-write of the output).
+//
+// Every hop runs through the same projection and link multiply as dwf_dhop, in the same order,
+// so the decomposed apply equals dwf_dhop bit for bit.
+#include <algorithm>
+#include <vector>
+
 #include "dwf_dhop_core.h"
 
 namespace dwf {
 
-// Zero the 9 complex entries of direction dir for link-table rows [r0, r0 + n).
-__global__ void __launch_bounds__(256) k_zero_links(unsigned *links, long r0, long n, int dir, int words) {
-    const long t = (long)blockIdx.x * 256 + threadIdx.x;
-    if (t >= n * words) return;
-    const long r = r0 + t / words;
-    const int k = (int)(t % words);
-    links[(r * 8 + dir) * words + k] = 0u;
+constexpr int kDdSegs = 8;  // face segments: 2 * mu + side (side 0: slice x_mu = 0, 1: x_mu = L_mu - 1)
+
+struct FaceGeom {
+    unsigned L0h, L1, L2, L3;
+    int Ls, parity;  // output parity p; faces hold input sites (parity 1 - p)
+    unsigned cut;
+    long seg_off[kDdSegs + 1];  // first face site of each segment, prefix sums (empty for uncut mu)
+};
+
+// Input checkerboard row of face site i of segment seg (see the file comment).
+__device__ __forceinline__ long face_src_row(const FaceGeom &f, int seg, long i) {
+    const int mu = seg >> 1, side = seg & 1;
+    const unsigned q = 1u - (unsigned)f.parity;
+    unsigned xh, y, z, t;
+    if (mu == 0) {
+        const unsigned yh2 = f.L1 / 2;
+        const unsigned yh = (unsigned)(i % yh2), zt = (unsigned)(i / yh2);
+        z = zt % f.L2;
+        t = zt / f.L2;
+        const unsigned xs = side ? 2 * f.L0h - 1 : 0;
+        y = 2 * yh + ((q + xs + z + t) & 1u);
+        xh = xs >> 1;
+    } else {
+        xh = (unsigned)(i % f.L0h);
+        const unsigned r = (unsigned)(i / f.L0h);
+        if (mu == 1) {
+            z = r % f.L2;
+            t = r / f.L2;
+            y = side ? f.L1 - 1 : 0;
+        } else if (mu == 2) {
+            y = r % f.L1;
+            t = r / f.L1;
+            z = side ? f.L2 - 1 : 0;
+        } else {
+            y = r % f.L1;
+            z = r / f.L1;
+            t = side ? f.L3 - 1 : 0;
+        }
+    }
+    return ((long)y + (long)f.L1 * ((long)z + (long)f.L2 * t)) * f.L0h + xh;
 }
 
-// Half spinors P^TAU_3 psi of the slice rows [r0, r0 + S) of an input field, as
-// face[i][s][12 reals] in the arithmetic type.
-template <int PI, int TAU>
-__global__ void __launch_bounds__(256) k_face_gather(typename PT<PI>::A *face, const char *in, long r0, long S,
-                                                     int Ls) {
+// Face site index of the input site reached from output site (x0..x3, xh) across cut mu.
+__device__ __forceinline__ long face_index(const FaceGeom &f, int mu, unsigned xh, unsigned x1, unsigned x2,
+                                           unsigned x3) {
+    if (mu == 0) return (long)(x1 >> 1) + (long)(f.L1 / 2) * ((long)x2 + (long)f.L2 * x3);
+    if (mu == 1) return (long)xh + (long)f.L0h * ((long)x2 + (long)f.L2 * x3);
+    if (mu == 2) return (long)xh + (long)f.L0h * ((long)x1 + (long)f.L1 * x3);
+    return (long)xh + (long)f.L0h * ((long)x1 + (long)f.L1 * x2);
+}
+
+// All faces in one launch: lane (face site, s) of the concatenated segments.
+template <int PI, int DAG>
+__global__ void __launch_bounds__(256) k_dd_faces(typename PT<PI>::A *send, const char *in, const FaceGeom f) {
     using A = typename PT<PI>::A;
     constexpr int NG = 12 / PT<PI>::G;
+    constexpr int SG = DAG ? 1 : -1;  // projector sign of the forward hops
     const long t = (long)blockIdx.x * 256 + threadIdx.x;
-    if (t >= S * Ls) return;
-    const long i = t / Ls;
-    const int s = (int)(t - i * Ls);
+    const long site = t / f.Ls;
+    if (site >= f.seg_off[kDdSegs]) return;
+    const int s = (int)(t - site * f.Ls);
+    int seg = 0;
+    while (site >= f.seg_off[seg + 1]) ++seg;
+    const long row = face_src_row(f, seg, site - f.seg_off[seg]);
     u32x4 v[NG];
-    const long off = spinor_off<PI, long>(r0 + i, Ls, s);
+    const long off = spinor_off<PI, long>(row, f.Ls, s);
 #pragma unroll
-    for (int g = 0; g < NG; ++g) v[g] = *(const u32x4 *)(in + off + (long)g * Ls * 16);
+    for (int g = 0; g < NG; ++g) v[g] = *(const u32x4 *)(in + off + (long)g * f.Ls * 16);
     A h[12];
-    project_vecs<PI, 3, TAU>(v, h);
-    A *f = face + t * 12;
+    switch (seg) {
+        case 0: project_vecs<PI, 0, SG>(v, h); break;
+        case 1: project_vecs<PI, 0, -SG>(v, h); break;
+        case 2: project_vecs<PI, 1, SG>(v, h); break;
+        case 3: project_vecs<PI, 1, -SG>(v, h); break;
+        case 4: project_vecs<PI, 2, SG>(v, h); break;
+        case 5: project_vecs<PI, 2, -SG>(v, h); break;
+        case 6: project_vecs<PI, 3, SG>(v, h); break;
+        default: project_vecs<PI, 3, -SG>(v, h); break;
+    }
+    A *dst = send + t * 12;
 #pragma unroll
-    for (int k = 0; k < 12; ++k) f[k] = h[k];
+    for (int k = 0; k < 12; ++k) dst[k] = h[k];
 }
 
-// out(r0 + i, s) += reconstruct(W(r0 + i, dir) face[i][s]) for the boundary rows of one face.
-template <int PI, int DIR, int TAU>
-__global__ void __launch_bounds__(256) k_face_apply(char *out, const char *links, const typename PT<PI>::A *face,
-                                                    long r0, long S, int Ls) {
+// Boundary sites: the whole stencil, hops across a cut from the received faces.
+template <int PI, int DAG>
+__global__ void __launch_bounds__(256) k_dd_exterior(char *out, const char *in, const char *links,
+                                                     const typename PT<PI>::A *recv, const unsigned *blist, long nb,
+                                                     const FaceGeom f) {
     using A = typename PT<PI>::A;
+    constexpr int NG = 12 / PT<PI>::G;
+    constexpr int SG = DAG ? 1 : -1;
     const long t = (long)blockIdx.x * 256 + threadIdx.x;
-    if (t >= S * Ls) return;
-    const long i = t / Ls;
-    const int s = (int)(t - i * Ls);
-    const long c = r0 + i;
-    A w[18], h[12], acc[24];
-    load_link<PI>(links, c, DIR, w);
-    const A *f = face + t * 12;
+    const long b = t / f.Ls;
+    if (b >= nb) return;
+    const int s = (int)(t - b * f.Ls);
+    const long c = blist[b];
+    const unsigned L0h = f.L0h, L0 = 2 * L0h, L1 = f.L1, L2 = f.L2, L3 = f.L3;
+    const long rest = c / L0h;
+    const unsigned xh = (unsigned)(c - rest * L0h);
+    const unsigned x1 = (unsigned)(rest % L1), x2 = (unsigned)((rest / L1) % L2), x3 = (unsigned)(rest / ((long)L1 * L2));
+    const unsigned x0 = 2 * xh + (((unsigned)f.parity + x1 + x2 + x3) & 1u);
+    const unsigned xs[4] = {x0, x1, x2, x3}, Ln[4] = {L0, L1, L2, L3};
+    const long st[4] = {1, (long)L1, (long)L1 * L2, (long)L1 * L2 * L3};  // row strides of y, z, t
+    A acc[24];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) h[k] = f[k];
-    const long off = spinor_off<PI, long>(c, Ls, s);
-    load_spinor_off<PI>(out, off, Ls * 16, acc);
-    mul_reconstruct<3, TAU>(w, h, acc);
-    store_spinor_off<PI>(out, off, Ls * 16, acc, false);
+    for (int k = 0; k < 24; ++k) acc[k] = 0;
+#define DWF_DD_HOP(DIR, MU, TAU, FWD)                                                                   \
+    {                                                                                                  \
+        const bool cross = ((f.cut >> MU) & 1u) && (FWD ? xs[MU] + 1 == Ln[MU] : xs[MU] == 0);         \
+        A w[18], h[12];                                                                                \
+        load_link<PI>(links, c, DIR, w);                                                               \
+        if (cross) {                                                                                   \
+            const int seg = 2 * MU + (FWD ? 0 : 1);                                                    \
+            const A *src = recv + ((f.seg_off[seg] + face_index(f, MU, xh, x1, x2, x3)) * f.Ls + s) * 12; \
+            _Pragma("unroll") for (int k = 0; k < 12; ++k) h[k] = src[k];                             \
+        } else {                                                                                       \
+            long nbr;                                                                                  \
+            if (MU == 0) {                                                                             \
+                const unsigned xn = FWD ? (x0 + 1 == L0 ? 0 : x0 + 1) : (x0 == 0 ? L0 - 1 : x0 - 1);   \
+                nbr = rest * L0h + (xn >> 1);                                                          \
+            } else {                                                                                   \
+                const long d = FWD ? (xs[MU] + 1 == Ln[MU] ? -(long)(Ln[MU] - 1) : 1)                  \
+                                   : (xs[MU] == 0 ? (long)(Ln[MU] - 1) : -1);                          \
+                nbr = (rest + d * st[MU - 1]) * L0h + xh;                                              \
+            }                                                                                          \
+            u32x4 v[NG];                                                                               \
+            const long off = spinor_off<PI, long>(nbr, f.Ls, s);                                       \
+            _Pragma("unroll") for (int g = 0; g < NG; ++g) v[g] = *(const u32x4 *)(in + off + (long)g * f.Ls * 16); \
+            project_vecs<PI, MU, TAU>(v, h);                                                           \
+        }                                                                                              \
+        mul_reconstruct<MU, TAU>(w, h, acc);                                                           \
+    }
+    DWF_DD_HOP(0, 0, SG, true)
+    DWF_DD_HOP(1, 1, SG, true)
+    DWF_DD_HOP(2, 2, SG, true)
+    DWF_DD_HOP(3, 3, SG, true)
+    DWF_DD_HOP(4, 0, -SG, false)
+    DWF_DD_HOP(5, 1, -SG, false)
+    DWF_DD_HOP(6, 2, -SG, false)
+    DWF_DD_HOP(7, 3, -SG, false)
+#undef DWF_DD_HOP
+    store_spinor_off<PI>(out, spinor_off<PI, long>(c, f.Ls, s), f.Ls * 16, acc, false);
 }
 
 }  // namespace dwf
@@ -75,10 +179,12 @@ __global__ void __launch_bounds__(256) k_face_apply(char *out, const char *links
 struct dwf_dd_s {
     dwf_ctx ctx = nullptr;
     int prec = 0;
-    void *cut[2] = {};      // link tables per output parity, boundary t-links zeroed
-    void *send[2] = {};     // [0]: forward face (slice t = 0), [1]: backward face (slice t = Lt-1)
-    void *recv[2] = {};
+    unsigned cut = 0;
+    long seg_off[dwf::kDdSegs + 1] = {};
+    void *send = nullptr, *recv = nullptr;  // all faces, concatenated by segment
     size_t face_bytes = 0;
+    unsigned *blist[2] = {};  // boundary output sites (checkerboard rows) per output parity
+    long nb[2] = {};
     hipStream_t comm = nullptr;
     hipEvent_t ready = nullptr, halo = nullptr;
 };
@@ -88,9 +194,9 @@ namespace dwf {
 int dd_destroy(dwf_dd d) {
     if (!d) return DWF_OK;
     (void)hipDeviceSynchronize();
-    for (void *p : d->cut) (void)hipFree(p);
-    for (void *p : d->send) (void)hipFree(p);
-    for (void *p : d->recv) (void)hipFree(p);
+    (void)hipFree(d->send);
+    (void)hipFree(d->recv);
+    for (unsigned *p : d->blist) (void)hipFree(p);
     if (d->comm) (void)hipStreamDestroy(d->comm);
     if (d->ready) (void)hipEventDestroy(d->ready);
     if (d->halo) (void)hipEventDestroy(d->halo);
@@ -98,104 +204,125 @@ int dd_destroy(dwf_dd d) {
     return DWF_OK;
 }
 
-int dd_create(dwf_ctx ctx, int prec, dwf_dd *out) {
+int dd_create(dwf_ctx ctx, int prec, unsigned cut, dwf_dd *out) {
     const Geom &g = ctx->g;
     dwf_dd d = new (std::nothrow) dwf_dd_s();
     if (!d) return fail(DWF_ENOMEM, "dwf_dd_create: out of host memory");
     d->ctx = ctx;
     d->prec = prec;
-    const long S = g.half / g.L[3];  // checkerboard rows per t-slice
-    const size_t areal = prec == DWF_F64 ? 8 : 4;
-    d->face_bytes = (size_t)S * g.Ls * 12 * areal;
+    d->cut = cut;
     auto bail = [&](int code, const char *msg) {
         dd_destroy(d);
         return fail(code, msg);
     };
-    const size_t lb = link_bytes(g, prec);
-    for (int p = 0; p < 2; ++p)
-        if (hipMalloc(&d->cut[p], lb) != hipSuccess) return bail(DWF_ENOMEM, "dwf_dd_create: hipMalloc failed");
-    for (int k = 0; k < 2; ++k)
-        if (hipMalloc(&d->send[k], d->face_bytes) != hipSuccess || hipMalloc(&d->recv[k], d->face_bytes) != hipSuccess)
-            return bail(DWF_ENOMEM, "dwf_dd_create: hipMalloc failed");
+    // face segments: V / (2 L_mu) input sites per face of a cut direction
+    d->seg_off[0] = 0;
+    for (int seg = 0; seg < kDdSegs; ++seg) {
+        const int mu = seg >> 1;
+        d->seg_off[seg + 1] = d->seg_off[seg] + (((cut >> mu) & 1u) ? g.half / g.L[mu] : 0);
+    }
+    const size_t areal = prec == DWF_F64 ? 8 : 4;
+    d->face_bytes = (size_t)d->seg_off[kDdSegs] * g.Ls * 12 * areal;
+    if (hipMalloc(&d->send, d->face_bytes) != hipSuccess || hipMalloc(&d->recv, d->face_bytes) != hipSuccess)
+        return bail(DWF_ENOMEM, "dwf_dd_create: hipMalloc of the face buffers failed");
+    // boundary output sites of each parity
+    const unsigned L0 = g.L[0], L1 = g.L[1], L2 = g.L[2], L3 = g.L[3], L0h = L0 / 2;
+    for (int p = 0; p < 2; ++p) {
+        std::vector<unsigned> list;
+        for (long c = 0; c < g.half; ++c) {
+            const long rest = c / L0h;
+            const unsigned xh = (unsigned)(c - rest * L0h);
+            const unsigned x1 = (unsigned)(rest % L1), x2 = (unsigned)((rest / L1) % L2),
+                           x3 = (unsigned)(rest / ((long)L1 * L2));
+            const unsigned x0 = 2 * xh + ((p + x1 + x2 + x3) & 1u);
+            const bool bnd = ((cut & 1u) && (x0 == 0 || x0 + 1 == L0)) || ((cut & 2u) && (x1 == 0 || x1 + 1 == L1)) ||
+                             ((cut & 4u) && (x2 == 0 || x2 + 1 == L2)) || ((cut & 8u) && (x3 == 0 || x3 + 1 == L3));
+            if (bnd) list.push_back((unsigned)c);
+        }
+        d->nb[p] = (long)list.size();
+        if (hipMalloc(&d->blist[p], std::max<size_t>(1, list.size()) * sizeof(unsigned)) != hipSuccess)
+            return bail(DWF_ENOMEM, "dwf_dd_create: hipMalloc of the boundary list failed");
+        if (!list.empty() && hipMemcpy(d->blist[p], list.data(), list.size() * sizeof(unsigned),
+                                       hipMemcpyHostToDevice) != hipSuccess)
+            return bail(DWF_EHIP, "dwf_dd_create: copy of the boundary list failed");
+    }
     if (hipStreamCreateWithFlags(&d->comm, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&d->ready, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&d->halo, hipEventDisableTiming) != hipSuccess)
         return bail(DWF_EHIP, "dwf_dd_create: stream or event creation failed");
-    // cut tables: forward t-link (dir 3) of the last slice and backward t-link (dir 7) of the first
-    const int words = 9 * 2 * real_bytes(prec) / 4;
-    const unsigned nb = (unsigned)((S * words + 255) / 256);
-    for (int p = 0; p < 2; ++p) {
-        if (hipMemcpy(d->cut[p], ctx->links[prec][p], lb, hipMemcpyDeviceToDevice) != hipSuccess)
-            return bail(DWF_EHIP, "dwf_dd_create: link copy failed");
-        hipLaunchKernelGGL(k_zero_links, nb, 256, 0, 0, (unsigned *)d->cut[p], (long)(g.L[3] - 1) * S, S, 3, words);
-        hipLaunchKernelGGL(k_zero_links, nb, 256, 0, 0, (unsigned *)d->cut[p], 0L, S, 7, words);
-    }
-    if (hipDeviceSynchronize() != hipSuccess) return bail(DWF_EHIP, "dwf_dd_create: cutting the link tables failed");
     *out = d;
     return DWF_OK;
 }
 
+static FaceGeom face_geom(const dwf_dd d, int out_parity) {
+    const Geom &g = d->ctx->g;
+    FaceGeom f;
+    f.L0h = (unsigned)(g.L[0] / 2);
+    f.L1 = (unsigned)g.L[1];
+    f.L2 = (unsigned)g.L[2];
+    f.L3 = (unsigned)g.L[3];
+    f.Ls = g.Ls;
+    f.parity = out_parity;
+    f.cut = d->cut;
+    for (int k = 0; k <= kDdSegs; ++k) f.seg_off[k] = d->seg_off[k];
+    return f;
+}
+
 template <int PI>
-static int dd_faces(dwf_dd d, char *out, const char *in, int dagger, long S, int Ls, int L3, hipStream_t st,
-                    int stage) {
+static int dd_launch(dwf_dd d, char *out, const char *in, int out_parity, int dagger, hipStream_t st, int stage) {
     using A = typename PT<PI>::A;
-    const unsigned nb = (unsigned)((S * Ls + 255) / 256);
-    const long last = (long)(L3 - 1) * S;
-    if (stage == 0) {  // gather the faces the t-neighbours need
-        if (dagger) {
-            hipLaunchKernelGGL((k_face_gather<PI, 1>), nb, 256, 0, st, (A *)d->send[0], in, 0L, S, Ls);
-            hipLaunchKernelGGL((k_face_gather<PI, -1>), nb, 256, 0, st, (A *)d->send[1], in, last, S, Ls);
-        } else {
-            hipLaunchKernelGGL((k_face_gather<PI, -1>), nb, 256, 0, st, (A *)d->send[0], in, 0L, S, Ls);
-            hipLaunchKernelGGL((k_face_gather<PI, 1>), nb, 256, 0, st, (A *)d->send[1], in, last, S, Ls);
-        }
-    } else {  // boundary sites add the received halo
-        const char *lk = (const char *)d->ctx->links[PI][stage - 1];
-        if (dagger) {
-            hipLaunchKernelGGL((k_face_apply<PI, 3, 1>), nb, 256, 0, st, out, lk, (const A *)d->recv[0], last, S, Ls);
-            hipLaunchKernelGGL((k_face_apply<PI, 7, -1>), nb, 256, 0, st, out, lk, (const A *)d->recv[1], 0L, S, Ls);
-        } else {
-            hipLaunchKernelGGL((k_face_apply<PI, 3, -1>), nb, 256, 0, st, out, lk, (const A *)d->recv[0], last, S, Ls);
-            hipLaunchKernelGGL((k_face_apply<PI, 7, 1>), nb, 256, 0, st, out, lk, (const A *)d->recv[1], 0L, S, Ls);
-        }
+    const FaceGeom f = face_geom(d, out_parity);
+    if (stage == 0) {  // every face the neighbour domains need
+        const long lanes = f.seg_off[kDdSegs] * f.Ls;
+        const unsigned nb = (unsigned)((lanes + 255) / 256);
+        if (dagger) hipLaunchKernelGGL((k_dd_faces<PI, 1>), nb, 256, 0, st, (A *)d->send, in, f);
+        else hipLaunchKernelGGL((k_dd_faces<PI, 0>), nb, 256, 0, st, (A *)d->send, in, f);
+    } else {  // boundary sites from the received faces
+        const long n = d->nb[out_parity];
+        if (n == 0) return DWF_OK;
+        const unsigned nb = (unsigned)((n * f.Ls + 255) / 256);
+        const char *lk = (const char *)d->ctx->links[PI][out_parity];
+        if (dagger)
+            hipLaunchKernelGGL((k_dd_exterior<PI, 1>), nb, 256, 0, st, out, in, lk, (const A *)d->recv,
+                               d->blist[out_parity], n, f);
+        else
+            hipLaunchKernelGGL((k_dd_exterior<PI, 0>), nb, 256, 0, st, out, in, lk, (const A *)d->recv,
+                               d->blist[out_parity], n, f);
     }
     DWF_HIP(hipGetLastError());
     return DWF_OK;
 }
 
-static int dd_faces_any(dwf_dd d, char *out, const char *in, int dagger, int stage, hipStream_t st) {
-    const Geom &g = d->ctx->g;
-    const long S = g.half / g.L[3];
+static int dd_launch_any(dwf_dd d, char *out, const char *in, int out_parity, int dagger, hipStream_t st, int stage) {
     switch (d->prec) {
-        case DWF_F64: return dd_faces<DWF_F64>(d, out, in, dagger, S, g.Ls, g.L[3], st, stage);
-        case DWF_F32: return dd_faces<DWF_F32>(d, out, in, dagger, S, g.Ls, g.L[3], st, stage);
-        case DWF_F16: return dd_faces<DWF_F16>(d, out, in, dagger, S, g.Ls, g.L[3], st, stage);
-        default: return dd_faces<DWF_BF16>(d, out, in, dagger, S, g.Ls, g.L[3], st, stage);
+        case DWF_F64: return dd_launch<DWF_F64>(d, out, in, out_parity, dagger, st, stage);
+        case DWF_F32: return dd_launch<DWF_F32>(d, out, in, out_parity, dagger, st, stage);
+        case DWF_F16: return dd_launch<DWF_F16>(d, out, in, out_parity, dagger, st, stage);
+        default: return dd_launch<DWF_BF16>(d, out, in, out_parity, dagger, st, stage);
     }
 }
 
 int dd_dhop(dwf_dd d, void *out, const void *in, int out_parity, int dagger, hipStream_t st) {
     dwf_ctx ctx = d->ctx;
+    if (!ctx->gauge_set) return fail(DWF_EUNSUP, "dwf_dd_dhop: gauge not set");
     int rc;
-    // the comm stream starts once `in` is ready on the caller's stream
+    // the plan's stream starts once `in` is ready on the caller's stream: faces, exchange, exterior
     DWF_HIP(hipEventRecord(d->ready, st));
     DWF_HIP(hipStreamWaitEvent(d->comm, d->ready, 0));
-    if ((rc = dd_faces_any(d, nullptr, (const char *)in, dagger, 0, d->comm))) return rc;
-    // exchange with the t-neighbour domains (here: this one); forward face to the domain below,
-    // backward face to the domain above
-    DWF_HIP(hipMemcpyAsync(d->recv[0], d->send[0], d->face_bytes, hipMemcpyDeviceToDevice, d->comm));
-    DWF_HIP(hipMemcpyAsync(d->recv[1], d->send[1], d->face_bytes, hipMemcpyDeviceToDevice, d->comm));
+    if ((rc = dd_launch_any(d, nullptr, (const char *)in, out_parity, dagger, d->comm, 0))) return rc;
+    DWF_HIP(hipMemcpyAsync(d->recv, d->send, d->face_bytes, hipMemcpyDeviceToDevice, d->comm));
+    if ((rc = dd_launch_any(d, (char *)out, (const char *)in, out_parity, dagger, d->comm, 1))) return rc;
     DWF_HIP(hipEventRecord(d->halo, d->comm));
-    // interior on the caller's stream with the cut links, overlapping the faces
-    DhopCall c{in, out, nullptr, out_parity, dagger, EPI_SCALE, 1.0, 0.0, d->prec, d->prec};
-    c.links = d->cut[out_parity];
+    // interior on the caller's stream, overlapping the faces and the exchange
+    DhopCall c{in, out, nullptr, out_parity, dagger, EPI_INTERIOR, 1.0, 0.0, d->prec, d->prec};
+    c.dd_cut = d->cut;
     if ((rc = launch_dhop(ctx, c, ctx->shape[d->prec][dagger], st))) return rc;
     DWF_HIP(hipStreamWaitEvent(st, d->halo, 0));
-    return dd_faces_any(d, (char *)out, nullptr, dagger, 1 + out_parity, st);
+    return DWF_OK;
 }
 
-int dd_face_only(dwf_dd d, const void *in, int dagger, hipStream_t st) {
-    return dd_faces_any(d, nullptr, (const char *)in, dagger, 0, st);
+int dd_face_only(dwf_dd d, const void *in, int out_parity, int dagger, hipStream_t st) {
+    return dd_launch_any(d, nullptr, (const char *)in, out_parity, dagger, st, 0);
 }
 
 }  // namespace dwf

@@ -46,8 +46,16 @@ __global__ void __launch_bounds__(kMaxDhopThreads) k_dhop(const DhopArgs a) {
 
     const A alpha = (A)a.alpha;
     const Off zoff = spinor_off<PI, Off>(c, Ls, s);
-    if constexpr (EPI == EPI_SCALE) {
+    if constexpr (EPI == EPI_SCALE || EPI == EPI_INTERIOR) {
         if (!active) return;
+        if constexpr (EPI == EPI_INTERIOR) {
+            const Lat &g = a.lat;
+            const unsigned uc = (unsigned)c, rest = fdiv(uc, g.L0h, g.inv0h), xh = uc - rest * g.L0h;
+            const unsigned r2 = fdiv(rest, g.L1, g.inv1), x1 = rest - r2 * g.L1;
+            const unsigned x3 = fdiv(r2, g.L2, g.inv2), x2 = r2 - x3 * g.L2;
+            const unsigned x0 = 2 * xh + ((a.parity + x1 + x2 + x3) & 1);
+            if (dd_boundary(a.dd_cut, x0, x1, x2, x3, 2 * g.L0h, g.L1, g.L2, g.L3)) return;
+        }
 #pragma unroll
         for (int k = 0; k < 24; ++k) acc[k] *= alpha;
     } else if constexpr (EPI == EPI_AXPY) {
@@ -184,6 +192,14 @@ static int launch_t(const DhopArgs &a, int ls_t, long nblocks, int threads, hipS
 
 template <int PI, int PO>
 static int launch_pp(const DhopArgs &a, int ls_t, int dagger, int epi, long nb, int th, hipStream_t st) {
+    if (epi == EPI_INTERIOR) {
+        // the interior of a decomposed apply: same storage in and out
+        if constexpr (PI == PO) {
+            if (dagger) return launch_t<PI, PO, 1, EPI_INTERIOR>(a, ls_t, nb, th, st);
+            return launch_t<PI, PO, 0, EPI_INTERIOR>(a, ls_t, nb, th, st);
+        }
+        return fail(DWF_EUNSUP, "hopping kernel: the interior launch needs equal input and output precision");
+    }
     if (epi == EPI_CG) {
         // the solver's residual update: adjoint kernel, r in FP32 or FP64
         if constexpr (PO == DWF_F32 || PO == DWF_F64)
@@ -259,6 +275,7 @@ int launch_dhop(dwf_ctx ctx, const DhopCall &c, const DhopShape &shape_in, hipSt
     a.cg_live = c.cg_live;
     if (c.schur_coef) m5inv_setup(g, a.m5i, true);
     if (c.links) a.links = (const char *)c.links;
+    a.dd_cut = c.epi == EPI_INTERIOR ? c.dd_cut : 0u;
     if (c.epi == EPI_CG && (!c.norm_out || !c.cg_alpha || !c.cg_live || !c.z))
         return fail(DWF_EINVAL, "hopping kernel: CG epilogue needs z, partials and the solver scalars");
     int threads;

@@ -86,6 +86,8 @@ enum Epi {
                     // with DhopCall::schur_coef the Schur factor Mooee^-1 (b + c K) instead
     EPI_CG = 4,     // CG step: y = M5op(z) + alpha * D psi is A p; out (= r, FP32 or FP64, read and
                     // written) -= (*cg_alpha) * y when *cg_live != 0, with |r|^2 partials in norm_out
+    EPI_INTERIOR = 5,  // as EPI_SCALE, for the interior of a decomposed apply: output sites with a hop
+                       // across a cut (DhopCall::dd_cut) are not written (same input and output precision)
 };
 
 struct DhopCall {
@@ -102,6 +104,7 @@ struct DhopCall {
     const double *cg_alpha = nullptr, *cg_live = nullptr;  // EPI_CG: device scalars of the solver
     bool schur_coef = false;     // EPI_M5INV: apply Mooee^-1 (b + c K) (identical to Mooee^-1 for Shamir)
     const void *links = nullptr; // gathered link table to use instead of the context's (same layout)
+    unsigned dd_cut = 0;         // EPI_INTERIOR: cut directions, bit mu (x = 1, y = 2, z = 4, t = 8)
 };
 
 // Solver workspace (allocated on first solve).

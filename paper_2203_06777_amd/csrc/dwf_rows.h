@@ -37,7 +37,16 @@ struct DhopArgs {
     double *norm_out;
     const double *cg_alpha, *cg_live;
     M5InvCoef m5i;  // EPI_M5INV: Mooee^-1 (or the Moebius Schur factor)
+    unsigned dd_cut;  // EPI_INTERIOR: cut directions (bit mu)
 };
+
+// Whether an output site has a hop across a cut of a domain decomposition: its coordinate
+// along a cut direction mu is 0 (backward hop) or L_mu - 1 (forward hop).
+__device__ __forceinline__ bool dd_boundary(unsigned cut, unsigned x0, unsigned x1, unsigned x2, unsigned x3,
+                                            unsigned L0, unsigned L1, unsigned L2, unsigned L3) {
+    return ((cut & 1u) && (x0 == 0 || x0 + 1 == L0)) || ((cut & 2u) && (x1 == 0 || x1 + 1 == L1)) ||
+           ((cut & 4u) && (x2 == 0 || x2 + 1 == L2)) || ((cut & 8u) && (x3 == 0 || x3 + 1 == L3));
+}
 
 // Host side: fills the geometry, launch-shape and link fields of a for one output
 // parity (alpha = 1, no fields attached); returns whether the row-block kernel
@@ -161,6 +170,17 @@ __device__ __forceinline__ void row_block(const DhopArgs &a, unsigned q0, const 
     const bool active = t < nthr && q0 + r < a.nrows;
     unsigned x1 = 0, x2 = 0, x3 = 0;
     if (active) rowmap(a, q0 + r, x1, x2, x3);
+    if constexpr (EPI == EPI_INTERIOR) {
+        // a block whose rows all lie on a y, z or t cut has no interior site: the whole workgroup leaves
+        bool any = false;
+        const unsigned nr = min((unsigned)a.rows, a.nrows - q0);
+        for (unsigned rr = 0; rr < nr && !any; ++rr) {
+            unsigned y1, y2, y3;
+            rowmap(a, q0 + rr, y1, y2, y3);
+            any = !dd_boundary(a.dd_cut & 14u, 1, y1, y2, y3, 4, a.lat.L1, a.lat.L2, a.lat.L3);
+        }
+        if (!any) return;
+    }
     // row indices in the offset type (32-bit when every field is below 4 GiB; the
     // wrap-around steps are exact in modular arithmetic)
     const unsigned L0 = 2 * a.lat.L0h, L1 = a.lat.L1, L2 = a.lat.L2, L3 = a.lat.L3;
@@ -321,8 +341,9 @@ __device__ __forceinline__ void row_block(const DhopArgs &a, unsigned q0, const 
 
     const A alpha = (A)a.alpha;
     const Off zoff = spinor_off<PI, Off>(c, Ls, s);
-    if constexpr (EPI == EPI_SCALE) {
+    if constexpr (EPI == EPI_SCALE || EPI == EPI_INTERIOR) {
         if (!active) return;
+        if (EPI == EPI_INTERIOR && dd_boundary(a.dd_cut, x0, x1, x2, x3, L0, L1, L2, L3)) return;
 #pragma unroll
         for (int k = 0; k < 24; ++k) acc[k] *= alpha;
     } else if constexpr (EPI == EPI_AXPY) {

@@ -54,9 +54,9 @@ _SIGS = {
     "dwf_set_gauge": [_P, _P, _P],
     "dwf_set_mobius": [_P, _D, _D],
     "dwf_expi_links": [_P, _P, _P, _D, _P],
-    "dwf_dd_create": [_P, _I, ctypes.POINTER(_P)],
+    "dwf_dd_create": [_P, _I, _I, ctypes.POINTER(_P)],
     "dwf_dd_dhop": [_P, _P, _P, _I, _I, _P],
-    "dwf_dd_faces": [_P, _P, _I, _P],
+    "dwf_dd_faces": [_P, _P, _I, _I, _P],
     "dwf_dd_destroy": [_P],
     "dwf_gauge_axpy": [_P, _P, _D, _P, _P],
     "dwf_gauge_norm2": [_P, ctypes.POINTER(_D), _P, _P],
@@ -159,9 +159,14 @@ def dwf_get_mobius(ctx):
     return b.value, c.value
 
 
-def dwf_dd_create(ctx, prec):
+DWF_CUT = {"x": 1, "y": 2, "z": 4, "t": 8}
+
+
+def dwf_dd_create(ctx, prec, cuts="t"):
+    """cuts: a mask of DWF_CUT values or a string of the cut axes, e.g. "xyz" (the 2x2x2x1 split)."""
+    mask = cuts if isinstance(cuts, int) else sum(DWF_CUT[a] for a in set(cuts))
     d = _P()
-    _check(lib().dwf_dd_create(ctx, _prec(prec), ctypes.byref(d)))
+    _check(lib().dwf_dd_create(ctx, _prec(prec), int(mask), ctypes.byref(d)))
     return d
 
 
@@ -169,8 +174,8 @@ def dwf_dd_dhop(dd, out, inp, out_parity, dagger, stream=None):
     _check(lib().dwf_dd_dhop(dd, _ptr(out), _ptr(inp), int(out_parity), int(dagger), _stream(stream)))
 
 
-def dwf_dd_faces(dd, inp, dagger, stream=None):
-    _check(lib().dwf_dd_faces(dd, _ptr(inp), int(dagger), _stream(stream)))
+def dwf_dd_faces(dd, inp, out_parity, dagger, stream=None):
+    _check(lib().dwf_dd_faces(dd, _ptr(inp), int(out_parity), int(dagger), _stream(stream)))
 
 
 def dwf_dd_destroy(dd):

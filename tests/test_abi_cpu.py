@@ -109,8 +109,8 @@ def test_null_handles_of_the_extensions_are_errors():
     r = ctypes.c_double()
     assert l.dwf_gauge_norm2(None, ctypes.byref(r), None, None) == -1
     d = ctypes.c_void_p()
-    assert l.dwf_dd_create(None, 1, ctypes.byref(d)) == -1
+    assert l.dwf_dd_create(None, 1, 8, ctypes.byref(d)) == -1
     assert l.dwf_dd_dhop(None, None, None, 0, 0, None) == -1
     assert b"null plan" in l.dwf_last_error()
-    assert l.dwf_dd_faces(None, None, 0, None) == -1
+    assert l.dwf_dd_faces(None, None, 0, 0, None) == -1
     assert l.dwf_dd_destroy(None) == 0
