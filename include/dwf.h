@@ -97,7 +97,8 @@ typedef struct {
 /* ---- context ------------------------------------------------------------ */
 
 /* Validates geom, binds the current HIP device, allocates link storage for
- * all precisions and two FP64-sized checkerboard temporaries. */
+ * all precisions and two FP64-sized checkerboard temporaries.
+ * Paper: Introduction (the domain-wall operator as the case the data layout serves). */
 int dwf_create(const dwf_geom *geom, dwf_ctx *out);
 int dwf_destroy(dwf_ctx ctx);
 const char *dwf_last_error(void);
@@ -108,7 +109,8 @@ int dwf_field_bytes(dwf_ctx ctx, int prec, int full, size_t *bytes);
 /* Copies the canonical FP64 gauge field into the library's gathered link
  * tables (8 links per checkerboard site, backward links stored daggered,
  * eta folded in) in every precision.  U itself is not modified and may be
- * freed afterwards.  Any complex 3x3 matrices are accepted (not only SU(3)). */
+ * freed afterwards.  Any complex 3x3 matrices are accepted (not only SU(3)).
+ * Paper: Acceleration abstraction (the layout the stencil kernels read). */
 int dwf_set_gauge(dwf_ctx ctx, const double *U, void *stream);
 
 /* Switches the context to the Moebius operator with real coefficients b, c
@@ -136,26 +138,33 @@ int dwf_convert(dwf_ctx ctx, void *out, int out_prec, const void *in, int in_pre
 /* ---- operators (checkerboard fields unless stated) ------------------------ */
 
 /* out = D_h^{p<-1-p} in (dagger = 0) or (D_h^dag)^{p<-1-p} in (dagger = 1),
- * p = out_parity; the raw hopping term, no -1/2. in and out must not alias. */
+ * p = out_parity; the raw hopping term, no -1/2. in and out must not alias.
+ * Paper: Performance results, the Nsight Compute figure ("main kernel DWF code",
+ * bandwidth-bound), and the Conclusion's node-local Wilson matrix. */
 int dwf_dhop(dwf_ctx ctx, void *out, const void *in, int out_parity, int dagger, int prec, void *stream);
 
 /* out = M5op in, M5op^dag in, M5op^-1 in or M5op^-dag in (dagger, inverse in {0,1});
  * Mooee in place of M5op for a Moebius context;
- * full = 0: one checkerboard, full = 1: a full field.  in and out may alias. */
+ * full = 0: one checkerboard, full = 1: a full field.  in and out may alias.
+ * Paper: Conclusion (all kernels of the DWF Dirac operator bandwidth-saturating). */
 int dwf_m5(dwf_ctx ctx, void *out, const void *in, int dagger, int inverse, int full, int prec, void *stream);
 
-/* out = M_pc in (dagger = 0) or M_pc^dag in (dagger = 1) on the odd checkerboard. */
+/* out = M_pc in (dagger = 0) or M_pc^dag in (dagger = 1) on the odd checkerboard.
+ * Paper: Conclusion (the kernels of the DWF Dirac operator). */
 int dwf_mpc(dwf_ctx ctx, void *out, const void *in, int dagger, int prec, void *stream);
 
-/* out = M_pc^dag M_pc in on the odd checkerboard. */
+/* out = M_pc^dag M_pc in on the odd checkerboard: the normal operator CG applies.
+ * Paper: Performance results, the Nsight Compute figure (the main DWF kernel sequence). */
 int dwf_mdagm(dwf_ctx ctx, void *out, const void *in, int prec, void *stream);
 
-/* out = D_DW in (dagger = 0) or D_DW^dag in (dagger = 1) on full fields. */
+/* out = D_DW in (dagger = 0) or D_DW^dag in (dagger = 1) on full fields.
+ * Paper: Introduction (the domain-wall fermion operator). */
 int dwf_dw(dwf_ctx ctx, void *out, const void *in, int dagger, int prec, void *stream);
 
 /* ---- BLAS-1 and FP64 reductions (deterministic, fixed-order trees) -------- */
 
-/* *result (host) = sum |x|^2 accumulated in FP64. Synchronises the stream. */
+/* *result (host) = sum |x|^2 accumulated in FP64. Synchronises the stream.
+ * Paper: Acceleration abstraction, Internal API (the reduction primitive a solver needs). */
 int dwf_norm2(dwf_ctx ctx, double *result, const void *x, int full, int prec, void *stream);
 /* result[0] + i result[1] (host) = <x, y> = sum conj(x) y in FP64. Synchronises. */
 int dwf_cdot(dwf_ctx ctx, double *result, const void *x, const void *y, int full, int prec, void *stream);
@@ -173,7 +182,9 @@ int dwf_cdot_noalloc(dwf_ctx ctx, double *result, const void *x, const void *y, 
 /* y = (a_re + i a_im) x + y. */
 int dwf_axpy(dwf_ctx ctx, void *y, double a_re, double a_im, const void *x, int full, int prec, void *stream);
 
-/* ---- solvers -------------------------------------------------------------- */
+/* ---- solvers --------------------------------------------------------------
+ * The paper names no solver; CG on the Schur normal operator is what the DWF Dirac
+ * operator it profiles is applied by (Performance results: the operator sequence). */
 
 /* Solves M_pc^dag M_pc x = b on the odd checkerboard (FP64 internal fields),
  * starting from the x passed in, until ||b - A x|| / ||b|| <= tol (recomputed in FP64).
@@ -193,7 +204,10 @@ int dwf_cg_set_inner(dwf_ctx ctx, double inner_tol, int inner_maxit);
 int dwf_solve(dwf_ctx ctx, void *x, const void *b, int dagger, double tol, int maxit, int mode,
               dwf_cg_stats *stats, void *stream);
 
-/* ---- fermion force ---------------------------------------------------------- */
+/* ---- fermion force ----------------------------------------------------------
+ * Not in the paper: the derivative of the action with respect to the links, the
+ * differentiable form beside the operator (its outer products are the DWF stencil's
+ * transpose). */
 
 /* From full FP64 internal fields X, Y, writes canonical FP64 F (complex
  * [V][4][3][3]):  M_mu(x) = sum_s tr_spin[(1-gamma_mu) X(x+mu,s) Y(x,s)^dag],
@@ -250,7 +264,9 @@ int dwf_dd_dhop(dwf_dd dd, void *out, const void *in, int out_parity, int dagger
 int dwf_dd_faces(dwf_dd dd, const void *in, int out_parity, int dagger, void *stream);
 int dwf_dd_destroy(dwf_dd dd);
 
-/* ---- batched hopping term ---------------------------------------------------- */
+/* ---- batched hopping term ----------------------------------------------------
+ * Paper: Acceleration abstraction (one offloaded kernel over many sites; here over
+ * many fields and lattices in one graph launch). */
 
 /* A plan applies dwf_dhop (same out_parity, dagger and precision) to nrhs[i]
  * fields of each of nlat contexts (lattices may differ in volume and Ls) in
@@ -264,7 +280,9 @@ int dwf_batch_capture(dwf_batch plan, void *const *outs, const void *const *ins,
 int dwf_batch_launch(dwf_batch plan, void *stream);
 int dwf_batch_free(dwf_batch plan);
 
-/* ---- autotuning --------------------------------------------------------------- */
+/* ---- autotuning ---------------------------------------------------------------
+ * Paper: Acceleration abstraction, Offload primitives and attributes (launch shape as a
+ * per-kernel attribute). */
 
 /* Times the launch shapes of the hopping kernel for (prec, dagger) on this
  * context's lattice and keeps the fastest, separately for plain dwf_dhop
