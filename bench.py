@@ -33,7 +33,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2203_06777_amd/csrc/dhop.hip", "paper_2203_06777_amd/csrc/dwf_rows.h",
                   "paper_2203_06777_amd/csrc/dwf_dhop_core.h", "paper_2203_06777_amd/csrc/dwf_device.h",
-                  "paper_2203_06777_amd/csrc/dwf_spin.h", "paper_2203_06777_amd/csrc/dwf_common.h"]
+                  "paper_2203_06777_amd/csrc/dwf_spin.h", "paper_2203_06777_amd/csrc/dwf_common.h",
+                  "paper_2203_06777_amd/csrc/dwf_m5inv.h"]
 
 
 def log(msg):
@@ -46,6 +47,17 @@ def dhop_flops(vol, ls, nrhs=1):
 
 def dhop_bytes(vol, ls, real_bytes, nrhs=1):
     return (8 * 18 + nrhs * ls * 48) * real_bytes * (vol // 2)
+
+
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def kernel_source_sha():
@@ -258,10 +270,44 @@ def main():
         cpu = {"value": round(1320.0 * ls * nrow * passes / dt / 1e9, 3), "unit": "GFlop/s", "cores": nthreads,
                "kind": "oracle",
                "sample": f"plain C FP64 Dhop_cb (oracle) on the 32^4x16 input: {passes} whole applies "
-                         f"({nrow} output rows each), {dt:.1f} s"}
+                         f"({nrow} output rows each), {dt:.1f} s",
+               "host_cpu": host_cpu_model()}
+        # one core: a contiguous slice of the output rows of the same apply
+        C.set_num_threads(1)
+        nsl = nrow // 16
+        t = time.time()
+        C.dhop_cb(u, psi, 1, 0, rows=(0, nsl))
+        dt1 = time.time() - t
+        C.set_num_threads(nthreads)
+        cpu["one_core"] = {"value": round(1320.0 * ls * nsl / dt1 / 1e9, 3), "unit": "GFlop/s",
+                           "sample": f"{nsl} output rows of the 32^4x16 apply, {dt1:.1f} s"}
         log(f"cpu oracle: {cpu}")
     op.close()
     del u, psi
+    if cpu is not None:
+        # the other oracle timings of the hot path: 16^4 x 16 Dhop_cb and the 24^4 x 12 normal operator
+        w16 = F.WORKLOADS["dhop_16^4x16"]
+        u16 = F.gauge_field(w16["dims"], w16["eps"], w16["seed_u"])
+        p16 = F.fermion_cb(w16["dims"], w16["ls"], w16["seed_psi"])
+        reps, t = 0, time.time()
+        while reps < 3 or time.time() - t < 3.0:
+            C.dhop_cb(u16, p16, 1, 0)
+            reps += 1
+        dt16 = (time.time() - t) / reps
+        cpu["dhop_16^4x16"] = {"value": round(1320.0 * w16["ls"] * (16 ** 4 // 2) / dt16 / 1e9, 3),
+                               "unit": "GFlop/s", "sample": f"{reps} whole applies"}
+        del u16, p16
+        wc = F.WORKLOADS["cg_24^4x12"]
+        uc = F.gauge_field(wc["dims"], wc["eps"], wc["seed_u"])
+        bc = F.fermion_cb(wc["dims"], wc["ls"], wc["seed_psi"])
+        t = time.time()
+        C.mdagm(uc, bc, wc["M5"], wc["mf"])
+        dtm = time.time() - t
+        cpu["mdagm_24^4x12"] = {"seconds": round(dtm, 3),
+                                "note": "one M_pc^dag M_pc (4 Dhop_cb + M5op terms); a CG iteration is this plus "
+                                        "three vector passes, so FP64 CG to 1e-10 costs about iterations x this"}
+        del uc, bc
+        log(f"cpu oracle (other workloads): 16^4x16 {cpu['dhop_16^4x16']}, mdagm {cpu['mdagm_24^4x12']}")
 
     # ---------------- a5/a6: FP64 vs mixed CG at 24^4 x 12 ----------------
     if row_on("cg_24^4x12"):
@@ -338,28 +384,40 @@ def main():
     # ---------------- a7: batched graph launches ----------------
     if row_on("batched"):
         r = {}
-        g = torch.Generator(device="cuda").manual_seed(2040)
+
+        def same_as_singles(handles, ins, outs, nrhs):
+            """Every batched output equals the single-field dwf_dhop of the same input bit for bit."""
+            k, ok = 0, True
+            for li, h in enumerate(handles):
+                for _ in range(nrhs[li]):
+                    single = torch.empty_like(outs[k])
+                    D.dwf_dhop(h, single, ins[k], 0, 0, "f32")
+                    ok = ok and bool(torch.equal(single, outs[k]))
+                    k += 1
+            return ok
+
         w = F.WORKLOADS["batch_32^4x12x12"]
         bdims, bls = w["dims"], w["ls"]
         op3 = D.Context(bdims, bls, w["M5"], w["mf"])
         op3.set_gauge(torch.from_numpy(F.gauge_field(bdims, w["eps"], w["seed_u"])).cuda())
         nr = len(w["rhs_seeds"])
         ins, outs = [], []
-        for _ in range(nr):
-            p = torch.randn((vol // 2, bls, 4, 3), dtype=torch.complex128, device="cuda", generator=g)
-            ins.append(op3.pack(p, 1, "f32"))
+        for sd in w["rhs_seeds"]:  # the workload's seeds, 2040 + r
+            ins.append(op3.pack(torch.from_numpy(F.fermion_cb(bdims, bls, sd)).cuda(), 1, "f32"))
             outs.append(op3.field("f32"))
-            del p
         plan = D.dwf_batch_plan([op3.handle], [nr], "f32", 0)
         D.dwf_batch_capture(plan, outs, ins, 0)
         for _ in range(2):
             D.dwf_batch_launch(plan)
         ms = timed(lambda: D.dwf_batch_launch(plan), 5)
+        torch.cuda.synchronize()
+        same = same_as_singles([op3.handle], ins, outs, [nr])
         ms1 = timed(lambda: [D.dwf_dhop(op3.handle, outs[k], ins[k], 0, 0, "f32") for k in range(nr)], 3)
         fl = dhop_flops(vol, bls, nr)
         by = dhop_bytes(vol, bls, 4, nr)
         r["32^4x12x12rhs"] = {"graph_ms": round(ms, 3), "gflops": round(fl / (ms * 1e-3) / 1e9, 1),
-                               "gbs": round(by / (ms * 1e-3) / 1e9, 1), "per_rhs_launches_ms": round(ms1, 3)}
+                               "gbs": round(by / (ms * 1e-3) / 1e9, 1), "frac_hbm": round(by / (ms * 1e-3) / 8e12, 3),
+                               "per_rhs_launches_ms": round(ms1, 3), "bitwise_equal_to_single_applies": same}
         D.dwf_batch_free(plan)
         del ins, outs
         op3.close()
@@ -374,9 +432,8 @@ def main():
             ctxs.append(o)
             nrhs.append(len(lat["rhs_seeds"]))
             v = int(np.prod(ld))
-            for _ in lat["rhs_seeds"]:
-                p = torch.randn((v // 2, lls, 4, 3), dtype=torch.complex128, device="cuda", generator=g)
-                ins.append(o.pack(p, 1, "f32"))
+            for sd in lat["rhs_seeds"]:  # seeds 1000 L + r
+                ins.append(o.pack(torch.from_numpy(F.fermion_cb(ld, lls, sd)).cuda(), 1, "f32"))
                 outs.append(o.field("f32"))
             fl += dhop_flops(v, lls, nrhs[-1])
             by += dhop_bytes(v, lls, 4, nrhs[-1])
@@ -393,9 +450,12 @@ def main():
                     D.dwf_dhop(o.handle, outs[k], ins[k], 0, 0, "f32")
                     k += 1
 
+        torch.cuda.synchronize()
+        same = same_as_singles([c.handle for c in ctxs], ins, outs, nrhs)
         ms1 = timed(singles, 5)
         r["mixed_8_12_16_20x8x4rhs"] = {"graph_ms": round(ms, 4), "gflops": round(fl / (ms * 1e-3) / 1e9, 1),
-                                         "gbs": round(by / (ms * 1e-3) / 1e9, 1), "per_rhs_launches_ms": round(ms1, 4)}
+                                         "gbs": round(by / (ms * 1e-3) / 1e9, 1), "per_rhs_launches_ms": round(ms1, 4),
+                                         "bitwise_equal_to_single_applies": same}
         D.dwf_batch_free(plan)
         for c in ctxs:
             c.close()

@@ -43,6 +43,7 @@ def lib():
         l.oracle_mpc.argtypes = [P, P, P, P, i, d, d, i, i]
         l.oracle_mdagm.argtypes = [P, P, P, P, i, d, d, i]
         l.oracle_num_threads.restype = ctypes.c_int
+        l.oracle_set_num_threads.argtypes = [i]
         _lib = l
     return _lib
 
@@ -108,3 +109,7 @@ def mdagm(U, psi_o, M5, mf, antiperiodic_t=True):
 
 def num_threads() -> int:
     return lib().oracle_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    lib().oracle_set_num_threads(int(n))

@@ -229,3 +229,13 @@ int oracle_num_threads(void) {
     }
     return n;
 }
+
+/* Thread count of the later parallel regions (timing on one core or all of them). */
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
