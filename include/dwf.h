@@ -190,7 +190,10 @@ int dwf_axpy(dwf_ctx ctx, void *y, double a_re, double a_im, const void *x, int 
  * starting from the x passed in, until ||b - A x|| / ||b|| <= tol (recomputed in FP64).
  * mode 0: FP64 CG.  mode 1/2/3: FP64 defect correction around inner CG whose
  * operator stores spinors and links in FP32 / FP16 / BF16 (FP32 vectors,
- * FP64 reductions).  maxit bounds the total CG iterations.  stats may be NULL. */
+ * FP64 reductions); with FP32 the inner iteration keeps its search direction
+ * across each FP64 residual refresh (reliable update), the 16-bit ones restart
+ * from the refreshed residual.  maxit bounds the total CG iterations.  stats may
+ * be NULL. */
 int dwf_cg(dwf_ctx ctx, void *x, const void *b, double tol, int maxit, int mode, dwf_cg_stats *stats,
            void *stream);
 

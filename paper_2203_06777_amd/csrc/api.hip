@@ -168,6 +168,11 @@ int dwf_create(const dwf_geom *geom, dwf_ctx *out) {
         return cleanup(DWF_ENOMEM, "dwf_create: hipMalloc of reduction buffers failed");
     if (hipHostMalloc((void **)&c->host_scal, sizeof(double) * 16, hipHostMallocDefault) != hipSuccess)
         return cleanup(DWF_ENOMEM, "dwf_create: pinned host allocation failed");
+    // the solver's stop flag, written by the device straight into host memory
+    if (hipHostMalloc((void **)const_cast<double **>(&c->host_flag), sizeof(double) * 2, hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostGetDevicePointer((void **)&c->host_flag_dev, (void *)c->host_flag, 0) != hipSuccess)
+        return cleanup(DWF_ENOMEM, "dwf_create: mapped host allocation failed");
     for (int k = 0; k < 2; ++k)
         if (hipEventCreateWithFlags((hipEvent_t *)&c->events[k], hipEventDisableTiming) != hipSuccess)
             return cleanup(DWF_EHIP, "dwf_create: hipEventCreate failed");
@@ -188,6 +193,7 @@ int dwf_destroy(dwf_ctx c) {
     (void)hipFree(c->dhop_partials);
     (void)hipFree(c->scal);
     if (c->host_scal) (void)hipHostFree(c->host_scal);
+    if (c->host_flag) (void)hipHostFree((void *)c->host_flag);
     for (void *e : c->events)
         if (e) (void)hipEventDestroy((hipEvent_t)e);
     CgWork &w = c->work;

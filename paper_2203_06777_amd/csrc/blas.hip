@@ -66,6 +66,28 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce(double *partials, const 
     }
 }
 
+// r = b - ap (FP64) with the partials of |r|^2 in k_reduce's order: the true residual of
+// the defect correction in one pass.
+__global__ void __launch_bounds__(kRedThreads) k_residual64(double *partials, u32x4 *r, const u32x4 *b,
+                                                            const u32x4 *ap, long nv) {
+    double re = 0, im = 0;
+    for (long v = (long)blockIdx.x * kRedThreads + threadIdx.x; v < nv; v += (long)gridDim.x * kRedThreads) {
+        double bv[2], av[2];
+        unpack16<DWF_F64>(b[v], bv);
+        unpack16<DWF_F64>(ap[v], av);
+        bv[0] -= av[0];
+        bv[1] -= av[1];
+        r[v] = pack16<DWF_F64>(bv);
+        re += bv[0] * bv[0];
+        re += bv[1] * bv[1];
+    }
+    block_sum2(re, im);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = re;
+        partials[2 * blockIdx.x + 1] = im;
+    }
+}
+
 __global__ void __launch_bounds__(kRedThreads) k_finalize(double *dst, const double *partials, int nparts) {
     double re = 0, im = 0;
     for (int k = threadIdx.x; k < nparts; k += kRedThreads) {
@@ -167,6 +189,15 @@ int launch_reduce(double *partials, double *dst, const void *x, const void *y, l
     }
 #undef DWF_RED
     if (dst) hipLaunchKernelGGL(k_finalize, 1, kRedThreads, 0, st, dst, partials, kRedBlocks);
+    DWF_HIP(hipGetLastError());
+    return DWF_OK;
+}
+
+int launch_residual64(double *partials, double *dst, void *r, const void *b, const void *ap, long n, hipStream_t st) {
+    const long nv = nvec(n, DWF_F64);
+    hipLaunchKernelGGL(k_residual64, kRedBlocks, kRedThreads, 0, st, partials, (u32x4 *)r, (const u32x4 *)b,
+                       (const u32x4 *)ap, nv);
+    hipLaunchKernelGGL(k_finalize, 1, kRedThreads, 0, st, dst, partials, kRedBlocks);
     DWF_HIP(hipGetLastError());
     return DWF_OK;
 }

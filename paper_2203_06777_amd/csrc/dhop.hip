@@ -37,6 +37,7 @@ __global__ void __launch_bounds__(kMaxDhopThreads) k_dhop(const DhopArgs a) {
     const bool active = c < a.half;
     if constexpr (EPI == EPI_CG)
         if (*a.cg_live == 0) return;  // the solver has stopped: r stays as it is
+    if (a.stop != nullptr && *a.stop != 0) return;
 
     A acc[24];
 #pragma unroll
@@ -96,6 +97,7 @@ __global__ void __launch_bounds__(kMaxDhopThreads) k_dhop_rows(const DhopArgs a)
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     if constexpr (EPI == EPI_CG)
         if (*a.cg_live == 0) return;  // the solver has stopped: r stays as it is
+    if (a.stop != nullptr && *a.stop != 0) return;
     const long lb = a.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (long)blockIdx.x;
     row_block<PI, PO, DAG, EPI, LS>(a, (unsigned)lb * (unsigned)a.rows, a.in, a.out, a.links, smem);
 }
@@ -276,6 +278,7 @@ int launch_dhop(dwf_ctx ctx, const DhopCall &c, const DhopShape &shape_in, hipSt
     if (c.schur_coef) m5inv_setup(g, a.m5i, true);
     if (c.links) a.links = (const char *)c.links;
     a.dd_cut = c.epi == EPI_INTERIOR ? c.dd_cut : 0u;
+    a.stop = c.stop;
     if (c.epi == EPI_CG && (!c.norm_out || !c.cg_alpha || !c.cg_live || !c.z))
         return fail(DWF_EINVAL, "hopping kernel: CG epilogue needs z, partials and the solver scalars");
     int threads;

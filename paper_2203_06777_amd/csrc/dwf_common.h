@@ -105,6 +105,7 @@ struct DhopCall {
     bool schur_coef = false;     // EPI_M5INV: apply Mooee^-1 (b + c K) (identical to Mooee^-1 for Shamir)
     const void *links = nullptr; // gathered link table to use instead of the context's (same layout)
     unsigned dd_cut = 0;         // EPI_INTERIOR: cut directions, bit mu (x = 1, y = 2, z = 4, t = 8)
+    const double *stop = nullptr;  // device flag: when nonzero at launch the kernel does nothing
 };
 
 // Solver workspace (allocated on first solve).
@@ -127,6 +128,8 @@ struct dwf_ctx_s {
     double *dhop_partials = nullptr;  // one FP64 partial per hopping-kernel workgroup (V/2 doubles)
     double *scal = nullptr;      // device scalars of the solvers
     double *host_scal = nullptr; // pinned host mirror (16 doubles)
+    volatile double *host_flag = nullptr;  // mapped, coherent host memory: the CG stop flag
+    double *host_flag_dev = nullptr;       // its device address
     void *events[2] = {};        // hipEvent_t pair for the solver's lagged stop check
     dwf::DhopShape shape[4][2];        // tuned launch shape per (prec, dagger): plain hopping launches
     dwf::DhopShape shape_schur[4][2];  // the same for the fused Schur kernels (M5op, M5op^-1, CG epilogues)
@@ -174,15 +177,17 @@ int launch_m5_op(const Geom &g, void *out, const void *x, double d, double e, co
 int launch_reduce(double *partials, double *dst, const void *x, const void *y, long n, int prec, int dot,
                   hipStream_t st);
 int launch_axpy(void *y, double ar, double ai, const void *x, long n, int prec, hipStream_t st);
+// r = b - ap (FP64 fields of n complex numbers) and |r|^2 into dst[0], in launch_reduce's order.
+int launch_residual64(double *partials, double *dst, void *r, const void *b, const void *ap, long n, hipStream_t st);
 int launch_fill_pattern(void *f, size_t bytes, int prec, hipStream_t st);
 int launch_count_diff(const void *a, const void *b, size_t bytes, unsigned *count, hipStream_t st);
 
 // Operators composed from kernels (ops.hip).
 int op_mpc(dwf_ctx ctx, void *out, const void *in, int dagger, int prec, hipStream_t st, double *norm_out = nullptr,
-           long *nparts = nullptr);
+           long *nparts = nullptr, const double *stop = nullptr);
 int op_mdagm(dwf_ctx ctx, void *out, const void *in, int prec, void *tmp_o, hipStream_t st);
 int op_mpcdag_cg(dwf_ctx ctx, void *r, int prec_r, const void *y, int prec, const double *cg_alpha,
-                 const double *cg_live, double *partials, long *nparts, hipStream_t st);
+                 const double *cg_live, double *partials, long *nparts, hipStream_t st, const double *stop = nullptr);
 
 // Static reduction scratch of the no-allocation entry point (noalloc.hip): resolves its
 // device address on `device`, which must be current; once per device, thread-safe.

@@ -10,9 +10,10 @@
 //   beta, |r|^2, stop flag         one single-block kernel
 //   x += alpha p ; p = r + beta p  one streaming kernel
 // The scalars live in device memory.  The host reads the stop flag one
-// iteration behind (an async copy into pinned memory and an event), so the GPU
-// queue never drains; an iteration queued after the stop finds the live flag
-// cleared by its alpha kernel and leaves x, r and p untouched.  With a 16-bit
+// iteration behind (the beta kernel also writes it into mapped host memory; the host
+// waits on an event), so the GPU queue never drains; in an iteration queued after the stop every hopping kernel
+// finds the stop flag set and returns at once, the alpha kernel clears the live
+// flag, and x, r and p stay untouched.  With a 16-bit
 // operator the search direction is kept only in that format: it is the
 // hopping kernels' input, and x moves along exactly the p that A was applied to.
 #include <chrono>
@@ -68,18 +69,24 @@ __global__ void __launch_bounds__(kSumThreads) k_cg_alpha(double *scal, const do
     scal[S_LIVE] = 1;
 }
 
-// |r|^2 of the updated residual -> beta and the stop flag.
-__global__ void __launch_bounds__(kSumThreads) k_cg_beta(double *scal, const double *partials, long nparts) {
+// |r|^2 of the updated residual -> beta and the stop flag; the flag is also written to
+// host memory (host_done), which the host polls instead of copying the scalars back.
+__global__ void __launch_bounds__(kSumThreads) k_cg_beta(double *scal, const double *partials, long nparts,
+                                                         double *host_done) {
     const double rr = sum_partials(partials, nparts);
     if (threadIdx.x != 0 || scal[S_LIVE] == 0) return;
     scal[S_ITERS] += 1;
     if (!isfinite(rr)) {
         scal[S_DONE] = 2;
+        *host_done = 2;
         return;
     }
     scal[S_BETA] = rr / scal[S_RR];
     scal[S_RR] = rr;
-    if (rr <= scal[S_STOP]) scal[S_DONE] = 1;
+    if (rr <= scal[S_STOP]) {
+        scal[S_DONE] = 1;
+        *host_done = 1;
+    }
 }
 
 // x += alpha p ; p = r + beta p.  x and r in PV (FP64 or FP32), p in PP (PV, or the
@@ -229,11 +236,12 @@ static int norm2_sync(dwf_ctx ctx, const void *x, int prec, double *out, hipStre
     return DWF_OK;
 }
 
-// Plain CG iterations on A e = r from the current (x, r): p = r, until
-// |r|^2 <= stop_rr or the iteration budget is used.  vprec is the precision of
-// x and r (F64 or F32); oprec the operator's, which p is stored in.
+// CG iterations on A e = r from the current (x, r) until |r|^2 <= stop_rr or the
+// iteration budget is used: from p = r, or (keep_p) from the search direction p
+// the caller left in place.  vprec is the precision of x and r (F64 or F32);
+// oprec the operator's, which p is stored in.
 static int cg_core(dwf_ctx ctx, int vprec, int oprec, void *x, void *r, void *p, double stop_rr, int budget,
-                   int *iters_out, int *status_out, hipStream_t st) {
+                   bool keep_p, int *iters_out, int *status_out, hipStream_t st) {
     const Geom &g = ctx->g;
     const long n = g.half * g.Ls * 12;
     const unsigned nb = nb256(g.half * g.Ls);
@@ -245,17 +253,22 @@ static int cg_core(dwf_ctx ctx, int vprec, int oprec, void *x, void *r, void *p,
     // |r|^2 -> scal[S_RED] -> scal[S_RR]; p = r
     if ((rc = launch_reduce(ctx->partials, scal + S_RED, r, nullptr, n, vprec, 0, st))) return rc;
     hipLaunchKernelGGL(k_set_scalars, 1, 64, 0, st, scal, stop_rr);
-    if (oprec == vprec) DWF_HIP(hipMemcpyAsync(p, r, cb_bytes(g, vprec), hipMemcpyDeviceToDevice, st));
-    else if ((rc = launch_convert(g, p, oprec, r, vprec, 1, st))) return rc;
+    if (!keep_p) {
+        if (oprec == vprec) DWF_HIP(hipMemcpyAsync(p, r, cb_bytes(g, vprec), hipMemcpyDeviceToDevice, st));
+        else if ((rc = launch_convert(g, p, oprec, r, vprec, 1, st))) return rc;
+    }
     hipEvent_t ev[2] = {(hipEvent_t)ctx->events[0], (hipEvent_t)ctx->events[1]};
     double *hs = ctx->host_scal;
+    *ctx->host_flag = 0;  // the previous solve has drained the stream
     for (int it = 0; it < budget; ++it) {
         long np_y = 0, np_r = 0;
-        if ((rc = op_mpc(ctx, y, p, 0, oprec, st, parts, &np_y))) return rc;
+        // every hopping kernel of an iteration queued after the stop returns at once (S_DONE set)
+        if ((rc = op_mpc(ctx, y, p, 0, oprec, st, parts, &np_y, scal + S_DONE))) return rc;
         hipLaunchKernelGGL(k_cg_alpha, 1, kSumThreads, 0, st, scal, parts, np_y);
-        if ((rc = op_mpcdag_cg(ctx, r, vprec, y, oprec, scal + S_ALPHA, scal + S_LIVE, parts, &np_r, st)))
+        if ((rc = op_mpcdag_cg(ctx, r, vprec, y, oprec, scal + S_ALPHA, scal + S_LIVE, parts, &np_r, st,
+                               scal + S_DONE)))
             return rc;
-        hipLaunchKernelGGL(k_cg_beta, 1, kSumThreads, 0, st, scal, parts, np_r);
+        hipLaunchKernelGGL(k_cg_beta, 1, kSumThreads, 0, st, scal, parts, np_r, ctx->host_flag_dev);
         if (vprec == DWF_F64)
             hipLaunchKernelGGL((k_cg_px<DWF_F64, DWF_F64>), nb, 256, 0, st, x4, r4, p4, scal, g.half, g.Ls);
         else if (oprec == DWF_F16)
@@ -265,12 +278,12 @@ static int cg_core(dwf_ctx ctx, int vprec, int oprec, void *x, void *r, void *p,
         else
             hipLaunchKernelGGL((k_cg_px<DWF_F32, DWF_F32>), nb, 256, 0, st, x4, r4, p4, scal, g.half, g.Ls);
         DWF_HIP(hipGetLastError());
-        // stop flag, read one iteration behind
-        DWF_HIP(hipMemcpyAsync(hs + 8 * (it & 1), scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+        // stop flag, read one iteration behind: once iteration it - 1 has completed, the flag
+        // holds its stop decision (or a later one)
         DWF_HIP(hipEventRecord(ev[it & 1], st));
         if (it >= 1) {
             DWF_HIP(hipEventSynchronize(ev[(it - 1) & 1]));
-            if (hs[8 * ((it - 1) & 1) + S_DONE] != 0) break;
+            if (*ctx->host_flag != 0) break;
         }
     }
     DWF_HIP(hipStreamSynchronize(st));
@@ -304,18 +317,31 @@ int cg_solve(dwf_ctx ctx, void *x, const void *b, double tol, int maxit, int mod
         return finish(DWF_OK);
     }
     const int oprec = mode == 1 ? DWF_F32 : mode == 2 ? DWF_F16 : DWF_BF16;
-    // each inner solve gains two digits: short Krylov spaces, restarted from the FP64 residual
-    // (measured fastest for every inner precision on the 24^4 x 12 workload)
+    // Each inner solve gains two digits, then the residual is recomputed in FP64.  With the
+    // FP32 operator the iteration goes on from it with the search direction it had (a
+    // reliable update: the Krylov space is kept, 160 against 165 iterations of restarted
+    // inner solves on the 24^4 x 12 workload, where FP64 CG takes 158); a 16-bit direction
+    // carries too much rounding to be kept (172 against 165 iterations), so those restart
+    // from p = r.
     double inner_tol = ctx->inner_tol > 0 ? ctx->inner_tol : 1e-2;
     int inner_maxit = ctx->inner_maxit > 0 ? ctx->inner_maxit : 2000;
     int total = 0;
-    double rr = 0;
+    double rr = 0, prev_scale = 0, xx = 0;
+    if ((rc = norm2_sync(ctx, x, DWF_F64, &xx, st))) return rc;
+    bool x_zero = xx == 0.0;  // a zero start needs no operator application for its residual
     for (;;) {
         // r = b - A x (FP64)
-        if ((rc = op_mdagm(ctx, w.ap64, x, DWF_F64, ctx->tmp[1], st))) return rc;
-        DWF_HIP(hipMemcpyAsync(w.r64, b, b64, hipMemcpyDeviceToDevice, st));
-        if ((rc = launch_axpy(w.r64, -1.0, 0.0, w.ap64, n, DWF_F64, st))) return rc;
-        if ((rc = norm2_sync(ctx, w.r64, DWF_F64, &rr, st))) return rc;
+        if (x_zero) {
+            DWF_HIP(hipMemcpyAsync(w.r64, b, b64, hipMemcpyDeviceToDevice, st));
+            rr = bb;
+            x_zero = false;
+        } else {
+            if ((rc = op_mdagm(ctx, w.ap64, x, DWF_F64, ctx->tmp[1], st))) return rc;
+            if ((rc = launch_residual64(ctx->partials, ctx->scal + S_RED, w.r64, b, w.ap64, n, st))) return rc;
+            DWF_HIP(hipMemcpyAsync(ctx->host_scal, ctx->scal + S_RED, sizeof(double), hipMemcpyDeviceToHost, st));
+            DWF_HIP(hipStreamSynchronize(st));
+            rr = ctx->host_scal[0];
+        }
         s.true_rel_resid = std::sqrt(rr / bb);
         if (!std::isfinite(rr)) return finish(fail(DWF_ENAN, "dwf_cg: residual is not finite"));
         if (s.true_rel_resid <= tol) return finish(DWF_OK);
@@ -326,19 +352,34 @@ int cg_solve(dwf_ctx ctx, void *x, const void *b, double tol, int maxit, int mod
         s.outer_iters += 1;
         int it = 0, status = 0;
         if (mode == 0) {
-            if ((rc = cg_core(ctx, DWF_F64, DWF_F64, x, w.r64, w.p64, tol * tol * bb, maxit - total, &it, &status,
-                              st)))
+            if ((rc = cg_core(ctx, DWF_F64, DWF_F64, x, w.r64, w.p64, tol * tol * bb, maxit - total, false, &it,
+                              &status, st)))
                 return rc;
         } else {
             // inner solve A e = r^, r^ = r * sqrt(n)/|r| in FP32 (components of order one)
             const double scale = std::sqrt((double)n) / std::sqrt(rr);
-            hipLaunchKernelGGL((k_convert_scale<DWF_F64, DWF_F32>), nb256(g.half * g.Ls), 256, 0, st,
-                               (u32x4 *)w.r32, (const u32x4 *)w.r64, scale, g.half, g.Ls);
+            const unsigned nbv = nb256(g.half * g.Ls);
+            hipLaunchKernelGGL((k_convert_scale<DWF_F64, DWF_F32>), nbv, 256, 0, st, (u32x4 *)w.r32,
+                               (const u32x4 *)w.r64, scale, g.half, g.Ls);
             DWF_HIP(hipMemsetAsync(w.e32, 0, cb_bytes(g, DWF_F32), st));
             const int budget = std::min(inner_maxit, maxit - total);
             void *p = oprec == DWF_F32 ? w.p32 : w.p16;
-            if ((rc = cg_core(ctx, DWF_F32, oprec, w.e32, w.r32, p, inner_tol * inner_tol * (double)n, budget, &it,
-                              &status, st)))
+            const bool keep_p = oprec == DWF_F32 && prev_scale > 0;
+            if (keep_p) {  // the kept direction into the new scaling of the system
+                u32x4 *p4 = (u32x4 *)p;
+                const double f = scale / prev_scale;
+                if (oprec == DWF_F32)
+                    hipLaunchKernelGGL((k_convert_scale<DWF_F32, DWF_F32>), nbv, 256, 0, st, p4, p4, f, g.half, g.Ls);
+                else if (oprec == DWF_F16)
+                    hipLaunchKernelGGL((k_convert_scale<DWF_F16, DWF_F16>), nbv, 256, 0, st, p4, p4, f, g.half, g.Ls);
+                else
+                    hipLaunchKernelGGL((k_convert_scale<DWF_BF16, DWF_BF16>), nbv, 256, 0, st, p4, p4, f, g.half,
+                                       g.Ls);
+                DWF_HIP(hipGetLastError());
+            }
+            prev_scale = scale;
+            if ((rc = cg_core(ctx, DWF_F32, oprec, w.e32, w.r32, p, inner_tol * inner_tol * (double)n, budget, keep_p,
+                              &it, &status, st)))
                 return rc;
             hipLaunchKernelGGL(k_axpy_f32_to_f64, nb256(g.half * g.Ls), 256, 0, st, (u32x4 *)x,
                                (const u32x4 *)w.e32, 1.0 / scale, g.half, g.Ls);

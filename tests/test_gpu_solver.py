@@ -118,7 +118,8 @@ def test_full_solve(dagger, mode):
 
 @pytest.fixture(scope="module")
 def cg_workload():
-    """The CG workload (24^4 x 12, eps 0.3, tol 1e-10): context, source, and the FP64 solution."""
+    """The CG workload (24^4 x 12, eps 0.3, tol 1e-10): context, source, the FP64 solution and its
+    iteration count."""
     w = F.WORKLOADS["cg_24^4x12"]
     dims, ls = w["dims"], w["ls"]
     op, u = make(dims, ls, w["eps"], w["seed_u"], w["M5"], w["mf"])
@@ -128,14 +129,14 @@ def cg_workload():
     st = D().dwf_cg(op.handle, x, bi, w["tol"], 20000, 0)
     assert st["true_rel_resid"] <= w["tol"]
     x64 = op.unpack(x, 1, "f64").cpu().numpy()
-    yield w, op, u, b, bi, x64
+    yield w, op, u, b, bi, x64, st["inner_iters"]
     op.close()
     torch.cuda.empty_cache()
 
 
 def test_cg_24x24x24x24_fp64_residual_by_oracle(cg_workload):
     """The FP64 solver's solution, its residual recomputed by the C oracle."""
-    w, op, u, b, bi, x64 = cg_workload
+    w, op, u, b, bi, x64, _ = cg_workload
     r = b - C.mdagm(u, x64, w["M5"], w["mf"])
     assert np.linalg.norm(r) / np.linalg.norm(b) <= 2e-10
 
@@ -144,7 +145,7 @@ def test_cg_24x24x24x24_fp64_residual_by_oracle(cg_workload):
 def test_cg_24x24x24x24_mixed_agrees_with_fp64(cg_workload, mode):
     """The CG workload, defect correction with FP32 / FP16 / BF16 inner solves: the true residual
     reaches 1e-10 (recomputed by the oracle) and the solution agrees with FP64 CG to 1e-8."""
-    w, op, u, b, bi, x64 = cg_workload
+    w, op, u, b, bi, x64, fp64_iters = cg_workload
     x = op.zeros("f64")
     st = D().dwf_cg(op.handle, x, bi, w["tol"], 20000, mode)
     assert st["true_rel_resid"] <= w["tol"]
@@ -153,3 +154,27 @@ def test_cg_24x24x24x24_mixed_agrees_with_fp64(cg_workload, mode):
     assert rel(got, x64) <= 1e-8
     r = b - C.mdagm(u, got, w["M5"], w["mf"])
     assert np.linalg.norm(r) / np.linalg.norm(b) <= 2e-10
+    if mode == 1:
+        # the FP32 inner iteration keeps its search direction across the FP64 residual
+        # refreshes: its iteration count stays within a few percent of FP64 CG's
+        assert st["inner_iters"] <= 1.03 * fp64_iters
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_cg_from_a_nonzero_start(mode):
+    """A random initial guess: the first residual is b - A x0 (not b), and the solve still
+    reaches the oracle's solution."""
+    dims, ls = (4, 4, 4, 4), 8
+    op, u = make(dims, ls, seed_u=41)
+    b = F.fermion_cb(dims, ls, 42)
+    x0 = F.fermion_cb(dims, ls, 43)
+    want, _, res = R.cg(lambda v: R.mdagm(u, v, M5, MF), b, 1e-12, 5000)
+    bi = op.pack(to_dev(b), 1, "f64")
+    x = op.pack(to_dev(x0), 1, "f64")
+    st = D().dwf_cg(op.handle, x, bi, 1e-10, 5000, mode)
+    got = op.unpack(x, 1, "f64").cpu().numpy()
+    r = b - C.mdagm(u, got, M5, MF)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1.5e-10
+    assert rel(got, want) <= 1e-8
+    assert st["true_rel_resid"] <= 1e-10
+    op.close()
