@@ -511,6 +511,63 @@ def main():
             log(f"row hmc: {rh}")
         op4.close()
 
+    # ---------------- software-managed device cache: host fields beyond a device budget ----------------
+    if row_on("cache_16^4x16_f32"):
+        w = F.WORKLOADS["dhop_16^4x16"]
+        cdims, cls = w["dims"], w["ls"]
+        op5 = D.Context(cdims, cls, w["M5"], w["mf"])
+        op5.set_gauge(torch.from_numpy(F.gauge_field(cdims, w["eps"], w["seed_u"])).cuda())
+        base = op5.pack(torch.from_numpy(F.fermion_cb(cdims, cls, w["seed_psi"])).cuda(), 0, "f32")
+        nb = base.numel()
+        nf, slots, rounds = 8, 6, 3  # 8 input + 8 output fields in pinned host memory, device budget 6 fields
+        hin, hout = [], []
+        for i in range(nf):
+            d = (base.view(torch.float32) * (1.0 + 0.125 * i)).view(torch.uint8)
+            hin.append(torch.empty(nb, dtype=torch.uint8, pin_memory=True).copy_(d))
+            hout.append(torch.zeros(nb, dtype=torch.uint8, pin_memory=True))
+        dres_in, dres_out = base.clone(), op5.zeros("f32")
+        us_res = timed(lambda: D.dwf_dhop(op5.handle, dres_out, dres_in, 1, 0, "f32"), 20) * 1e3
+        h2d_ms = timed(lambda: dres_in.copy_(hin[0], non_blocking=True), 10)
+        cache = D.dwf_cache_create(slots * nb, D.DWF_CACHE_DEVICE)
+
+        def sweep():
+            for i in range(nf):
+                vi = D.dwf_cache_open(cache, hin[i], nb, D.DWF_ACC_READ)
+                vo = D.dwf_cache_open(cache, hout[i], nb, D.DWF_ACC_WRITE)
+                D.dwf_dhop(op5.handle, vo, vi, 1, 0, "f32")
+                D.dwf_cache_close(cache, hin[i])
+                D.dwf_cache_close(cache, hout[i])
+
+        sweep()  # fills the budget
+        torch.cuda.synchronize()
+        s0 = D.dwf_cache_get_stats(cache)
+        t = time.time()
+        for _ in range(rounds):
+            sweep()
+        torch.cuda.synchronize()
+        wall = time.time() - t
+        s1 = D.dwf_cache_get_stats(cache)
+        moved = (s1["h2d_bytes"] - s0["h2d_bytes"]) + (s1["d2h_bytes"] - s0["d2h_bytes"])
+        D.dwf_cache_open(cache, hout[nf - 1], nb, D.DWF_CPU_READ)
+        D.dwf_dhop(op5.handle, dres_out, dres_in.copy_(hin[nf - 1]), 1, 0, "f32")
+        same = bool(torch.equal(hout[nf - 1], dres_out.cpu()))
+        D.dwf_cache_close(cache, hout[nf - 1])
+        D.dwf_cache_destroy(cache)
+        rows["cache_16^4x16_f32"] = {
+            "fields_bytes": 2 * nf * nb, "device_budget_bytes": slots * nb,
+            "us_per_apply_through_cache": round(wall / (rounds * nf) * 1e6, 1),
+            "us_per_apply_resident": round(us_res, 1),
+            "migrated_gb_per_apply": round(moved / (rounds * nf) / 1e9, 4),
+            "migration_gbs": round(moved / wall / 1e9, 1),
+            "pinned_h2d_copy_gbs": round(nb / (h2d_ms * 1e-3) / 1e9, 1),
+            "evictions": s1["evictions"] - s0["evictions"],
+            "bitwise_equal_to_resident_apply": same,
+        }
+        log(f"row cache: {rows['cache_16^4x16_f32']}")
+        del hin, hout, dres_in, dres_out, base
+        op5.close()
+        torch.cuda.empty_cache()
+
     traffic, sha = measured_traffic()
     out = {
         "metric": "DWF Dhop GFlop/s & HBM GB/s on 1 GPU; mixed vs FP64 CG time-to-1e-8",

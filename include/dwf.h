@@ -299,6 +299,67 @@ int dwf_batch_free(dwf_batch plan);
  * stream. */
 int dwf_tune(dwf_ctx ctx, int prec, int dagger, double *best_us, void *stream);
 
+/* ---- software-managed device cache ------------------------------------------
+ * Paper: Memory models and software managed cache (the MemoryManager: a table of
+ * host buffers with their device copies, views opened with an access intent that
+ * migrate whole buffers, a device-memory high watermark, least-recently-used
+ * eviction and an "infrequently used" advice).
+ *
+ * A cache keeps device copies of HOST buffers (pinned memory from hipHostMalloc
+ * gives the fastest copies; pageable memory works).  dwf_cache_open returns a view
+ * of the buffer for one intent: the device address for DWF_ACC_READ / DWF_ACC_WRITE
+ * (valid until the view is closed), the host address for DWF_CPU_READ /
+ * DWF_CPU_WRITE.  It copies the whole buffer when the intent and the state ask for
+ * it (DWF_ST_*):
+ *   ACC_READ   Empty or CpuDirty: host -> device, then Consistent
+ *   ACC_WRITE  Empty or CpuDirty: host -> device (a read-write view), then AccDirty
+ *   CPU_READ   AccDirty: device -> host, then Consistent
+ *   CPU_WRITE  AccDirty: device -> host; then CpuDirty if a device copy exists
+ * A buffer is found by its host address; the first open registers it with its
+ * size, later opens must give the same size.  Views nest (a count per buffer);
+ * every open needs one dwf_cache_close.  The device bytes held (copies and freed
+ * blocks kept for reuse) never exceed watermark_bytes: to make room, buffers with
+ * no open view lose their device copy (written back first when AccDirty) in
+ * least-recently-opened order, buffers advised DWF_ADVISE_INFREQUENT before all
+ * others.  DWF_ENOMEM if every resident buffer has an open view.
+ *
+ * Copies are enqueued on `stream` (a hipStream_t); CPU intents, release, flush and
+ * destroy synchronise it, so the host may use a CPU view at once.  Use one stream
+ * per cache (or order the streams yourself); the host must not touch a registered
+ * buffer outside a CPU view.  backend DWF_CACHE_DEVICE uses device memory of the
+ * device current at dwf_cache_create; DWF_CACHE_HOST_SIM keeps the "device" copies
+ * in host memory (memcpy, no GPU): the same policy, for testing.  A cache may be
+ * used from one host thread at a time. */
+typedef struct dwf_cache_s *dwf_cache;
+enum { DWF_CPU_READ = 0, DWF_CPU_WRITE = 1, DWF_ACC_READ = 2, DWF_ACC_WRITE = 3 };
+enum { DWF_ST_EMPTY = 0, DWF_ST_CPU_DIRTY = 1, DWF_ST_ACC_DIRTY = 2, DWF_ST_CONSISTENT = 3 };
+enum { DWF_ADVISE_NORMAL = 0, DWF_ADVISE_INFREQUENT = 1 };
+enum { DWF_CACHE_DEVICE = 0, DWF_CACHE_HOST_SIM = 1 };
+
+typedef struct {
+    size_t watermark;          /* bytes */
+    size_t resident_bytes;     /* device copies of registered buffers */
+    size_t held_bytes;         /* resident_bytes plus freed blocks kept for reuse */
+    long long entries;         /* registered buffers */
+    long long h2d_count, d2h_count, evictions;
+    unsigned long long h2d_bytes, d2h_bytes;
+} dwf_cache_stats;
+
+int dwf_cache_create(size_t watermark_bytes, int backend, dwf_cache *out);
+int dwf_cache_open(dwf_cache c, void *host, size_t bytes, int intent, void **view, void *stream);
+int dwf_cache_close(dwf_cache c, void *host);
+/* DWF_ADVISE_INFREQUENT: evicted before every normally advised buffer. */
+int dwf_cache_advise(dwf_cache c, void *host, int advice);
+/* Writes back (if AccDirty) and forgets a buffer with no open view. */
+int dwf_cache_release(dwf_cache c, void *host, void *stream);
+/* Writes back every AccDirty buffer (they become Consistent). */
+int dwf_cache_flush(dwf_cache c, void *stream);
+/* state: DWF_ST_*; refs: open views; resident: whether a device copy exists (each may be NULL). */
+int dwf_cache_query(dwf_cache c, const void *host, int *state, int *refs, int *resident);
+int dwf_cache_get_stats(dwf_cache c, dwf_cache_stats *out);
+/* Writes back every AccDirty buffer and frees the device memory; no view may be open. */
+int dwf_cache_destroy(dwf_cache c, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -42,6 +42,22 @@ class dwf_cg_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class dwf_cache_stats(ctypes.Structure):
+    _fields_ = [("watermark", ctypes.c_size_t), ("resident_bytes", ctypes.c_size_t),
+                ("held_bytes", ctypes.c_size_t), ("entries", ctypes.c_longlong),
+                ("h2d_count", ctypes.c_longlong), ("d2h_count", ctypes.c_longlong),
+                ("evictions", ctypes.c_longlong), ("h2d_bytes", ctypes.c_ulonglong),
+                ("d2h_bytes", ctypes.c_ulonglong)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+DWF_CPU_READ, DWF_CPU_WRITE, DWF_ACC_READ, DWF_ACC_WRITE = 0, 1, 2, 3
+DWF_ST_EMPTY, DWF_ST_CPU_DIRTY, DWF_ST_ACC_DIRTY, DWF_ST_CONSISTENT = 0, 1, 2, 3
+DWF_ADVISE_NORMAL, DWF_ADVISE_INFREQUENT = 0, 1
+DWF_CACHE_DEVICE, DWF_CACHE_HOST_SIM = 0, 1
+
 _lib = None
 
 _P = ctypes.c_void_p
@@ -82,6 +98,15 @@ _SIGS = {
     "dwf_batch_launch": [_P, _P],
     "dwf_batch_free": [_P],
     "dwf_tune": [_P, _I, _I, ctypes.POINTER(_D), _P],
+    "dwf_cache_create": [ctypes.c_size_t, _I, ctypes.POINTER(_P)],
+    "dwf_cache_open": [_P, _P, ctypes.c_size_t, _I, ctypes.POINTER(_P), _P],
+    "dwf_cache_close": [_P, _P],
+    "dwf_cache_advise": [_P, _P, _I],
+    "dwf_cache_release": [_P, _P, _P],
+    "dwf_cache_flush": [_P, _P],
+    "dwf_cache_query": [_P, _P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)],
+    "dwf_cache_get_stats": [_P, ctypes.POINTER(dwf_cache_stats)],
+    "dwf_cache_destroy": [_P, _P],
 }
 
 
@@ -378,3 +403,68 @@ class Context:
         out = torch.empty(shape, dtype=torch.complex128, device="cuda")
         dwf_unpack(self.handle, out, internal, parity, prec)
         return out
+
+
+# ---- software-managed device cache (host buffers: CPU tensors or addresses) ----
+
+def _hptr(t) -> int:
+    if isinstance(t, int):
+        return t
+    if t.is_cuda:
+        raise ValueError("the cache keeps HOST buffers: pass a CPU tensor")
+    if not t.is_contiguous():
+        raise ValueError("host buffers must be contiguous")
+    return t.data_ptr()
+
+
+def _cstream(stream):
+    """torch's current stream when a GPU is present; the host stand-in backend needs none."""
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else None
+    return _stream(stream)
+
+
+def dwf_cache_create(watermark_bytes, backend=DWF_CACHE_DEVICE) -> int:
+    c = _P()
+    _check(lib().dwf_cache_create(int(watermark_bytes), int(backend), ctypes.byref(c)))
+    return c.value
+
+
+def dwf_cache_open(cache, host, nbytes, intent, stream=None) -> int:
+    """Address of the view: device memory for DWF_ACC_*, the host buffer for DWF_CPU_*."""
+    v = _P()
+    _check(lib().dwf_cache_open(cache, _hptr(host), int(nbytes), int(intent), ctypes.byref(v), _cstream(stream)))
+    return v.value
+
+
+def dwf_cache_close(cache, host):
+    _check(lib().dwf_cache_close(cache, _hptr(host)))
+
+
+def dwf_cache_advise(cache, host, advice):
+    _check(lib().dwf_cache_advise(cache, _hptr(host), int(advice)))
+
+
+def dwf_cache_release(cache, host, stream=None):
+    _check(lib().dwf_cache_release(cache, _hptr(host), _cstream(stream)))
+
+
+def dwf_cache_flush(cache, stream=None):
+    _check(lib().dwf_cache_flush(cache, _cstream(stream)))
+
+
+def dwf_cache_query(cache, host):
+    """(state DWF_ST_*, open views, resident on the device)."""
+    st, refs, res = _I(), _I(), _I()
+    _check(lib().dwf_cache_query(cache, _hptr(host), ctypes.byref(st), ctypes.byref(refs), ctypes.byref(res)))
+    return st.value, refs.value, bool(res.value)
+
+
+def dwf_cache_get_stats(cache) -> dict:
+    st = dwf_cache_stats()
+    _check(lib().dwf_cache_get_stats(cache, ctypes.byref(st)))
+    return st.as_dict()
+
+
+def dwf_cache_destroy(cache, stream=None):
+    _check(lib().dwf_cache_destroy(cache, _cstream(stream)))
