@@ -16,16 +16,18 @@
 //   interior  the hopping kernel writing only the output sites with no hop across a cut (a
 //             workgroup whose rows all lie on a y, z or t cut leaves at once), on the caller's
 //             stream, overlapping the faces and the exchange on the plan's stream.
-//   exterior  after the exchange, one lane per (boundary site, s) computes the whole stencil of
-//             its site, hops across a cut from the received half spinors and the rest from the
-//             local input, and writes the site (no read-modify-write of the output).
+//   exterior  after the exchange, the boundary output sites are computed whole, hops across a
+//             cut from the received half spinors and the rest from the local input, and written
+//             (no read-modify-write of the output): the rows on a y, z or t cut by the row-block
+//             kernel (EPI_EXTERIOR: its links and x-rows staged in LDS like every row launch),
+//             the remaining x-cut sites by a kernel with one lane per (site, s).
 //
 // Every hop runs through the same projection and link multiply as dwf_dhop, in the same order,
 // so the decomposed apply equals dwf_dhop bit for bit.
 #include <algorithm>
 #include <vector>
 
-#include "dwf_dhop_core.h"
+#include "dwf_rows.h"
 
 namespace dwf {
 
@@ -74,10 +76,7 @@ __device__ __forceinline__ long face_src_row(const FaceGeom &f, int seg, long i)
 // Face site index of the input site reached from output site (x0..x3, xh) across cut mu.
 __device__ __forceinline__ long face_index(const FaceGeom &f, int mu, unsigned xh, unsigned x1, unsigned x2,
                                            unsigned x3) {
-    if (mu == 0) return (long)(x1 >> 1) + (long)(f.L1 / 2) * ((long)x2 + (long)f.L2 * x3);
-    if (mu == 1) return (long)xh + (long)f.L0h * ((long)x2 + (long)f.L2 * x3);
-    if (mu == 2) return (long)xh + (long)f.L0h * ((long)x1 + (long)f.L1 * x3);
-    return (long)xh + (long)f.L0h * ((long)x1 + (long)f.L1 * x2);
+    return dd_face_index(mu, xh, x1, x2, x3, f.L0h, f.L1, f.L2);
 }
 
 // All faces in one launch: lane (face site, s) of the concatenated segments.
@@ -113,7 +112,7 @@ __global__ void __launch_bounds__(256) k_dd_faces(typename PT<PI>::A *send, cons
     for (int k = 0; k < 12; ++k) dst[k] = h[k];
 }
 
-// Boundary sites: the whole stencil, hops across a cut from the received faces.
+// Listed boundary sites: the whole stencil, hops across a cut from the received faces.
 template <int PI, int DAG>
 __global__ void __launch_bounds__(256) k_dd_exterior(char *out, const char *in, const char *links,
                                                      const typename PT<PI>::A *recv, const unsigned *blist, long nb,
@@ -183,8 +182,11 @@ struct dwf_dd_s {
     long seg_off[dwf::kDdSegs + 1] = {};
     void *send = nullptr, *recv = nullptr;  // all faces, concatenated by segment
     size_t face_bytes = 0;
-    unsigned *blist[2] = {};  // boundary output sites (checkerboard rows) per output parity
+    unsigned *blist[2] = {};  // boundary output sites left to the site kernel, per output parity
     long nb[2] = {};
+    unsigned *brows = nullptr;  // rows on a y, z or t cut (computed by the row kernel)
+    long nbrows = 0;
+    dwf::DhopShape row_shape;   // launch shape of the exterior rows
     hipStream_t comm = nullptr;
     hipEvent_t ready = nullptr, halo = nullptr;
 };
@@ -197,6 +199,7 @@ int dd_destroy(dwf_dd d) {
     (void)hipFree(d->send);
     (void)hipFree(d->recv);
     for (unsigned *p : d->blist) (void)hipFree(p);
+    (void)hipFree(d->brows);
     if (d->comm) (void)hipStreamDestroy(d->comm);
     if (d->ready) (void)hipEventDestroy(d->ready);
     if (d->halo) (void)hipEventDestroy(d->halo);
@@ -225,8 +228,26 @@ int dd_create(dwf_ctx ctx, int prec, unsigned cut, dwf_dd *out) {
     d->face_bytes = (size_t)d->seg_off[kDdSegs] * g.Ls * 12 * areal;
     if (hipMalloc(&d->send, d->face_bytes) != hipSuccess || hipMalloc(&d->recv, d->face_bytes) != hipSuccess)
         return bail(DWF_ENOMEM, "dwf_dd_create: hipMalloc of the face buffers failed");
-    // boundary output sites of each parity
+    // the exterior: rows on a y, z or t cut go to the row kernel when it applies to this lattice,
+    // the other boundary sites (x cut) to the site kernel
     const unsigned L0 = g.L[0], L1 = g.L[1], L2 = g.L[2], L3 = g.L[3], L0h = L0 / 2;
+    d->row_shape = ctx->shape[prec][0].rows > 0 ? ctx->shape[prec][0] : default_row_shape(g, prec, ctx->lds_limit);
+    const bool by_rows = d->row_shape.rows > 0 && row_shape_ok(g, d->row_shape, prec, ctx->lds_limit);
+    auto row_cut = [&](unsigned x1, unsigned x2, unsigned x3) {
+        return ((cut & 2u) && (x1 == 0 || x1 + 1 == L1)) || ((cut & 4u) && (x2 == 0 || x2 + 1 == L2)) ||
+               ((cut & 8u) && (x3 == 0 || x3 + 1 == L3));
+    };
+    if (by_rows) {
+        std::vector<unsigned> rows;
+        for (unsigned r = 0; r < L1 * L2 * L3; ++r)
+            if (row_cut(r % L1, (r / L1) % L2, r / (L1 * L2))) rows.push_back(r);
+        d->nbrows = (long)rows.size();
+        if (hipMalloc(&d->brows, std::max<size_t>(1, rows.size()) * sizeof(unsigned)) != hipSuccess)
+            return bail(DWF_ENOMEM, "dwf_dd_create: hipMalloc of the boundary rows failed");
+        if (!rows.empty() &&
+            hipMemcpy(d->brows, rows.data(), rows.size() * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess)
+            return bail(DWF_EHIP, "dwf_dd_create: copy of the boundary rows failed");
+    }
     for (int p = 0; p < 2; ++p) {
         std::vector<unsigned> list;
         for (long c = 0; c < g.half; ++c) {
@@ -235,9 +256,9 @@ int dd_create(dwf_ctx ctx, int prec, unsigned cut, dwf_dd *out) {
             const unsigned x1 = (unsigned)(rest % L1), x2 = (unsigned)((rest / L1) % L2),
                            x3 = (unsigned)(rest / ((long)L1 * L2));
             const unsigned x0 = 2 * xh + ((p + x1 + x2 + x3) & 1u);
-            const bool bnd = ((cut & 1u) && (x0 == 0 || x0 + 1 == L0)) || ((cut & 2u) && (x1 == 0 || x1 + 1 == L1)) ||
-                             ((cut & 4u) && (x2 == 0 || x2 + 1 == L2)) || ((cut & 8u) && (x3 == 0 || x3 + 1 == L3));
-            if (bnd) list.push_back((unsigned)c);
+            const bool on_row = row_cut(x1, x2, x3);
+            if (by_rows && on_row) continue;
+            if (on_row || ((cut & 1u) && (x0 == 0 || x0 + 1 == L0))) list.push_back((unsigned)c);
         }
         d->nb[p] = (long)list.size();
         if (hipMalloc(&d->blist[p], std::max<size_t>(1, list.size()) * sizeof(unsigned)) != hipSuccess)
@@ -272,6 +293,16 @@ template <int PI>
 static int dd_launch(dwf_dd d, char *out, const char *in, int out_parity, int dagger, hipStream_t st, int stage) {
     using A = typename PT<PI>::A;
     const FaceGeom f = face_geom(d, out_parity);
+    if (stage == 2) {  // boundary rows by the row kernel
+        if (d->nbrows == 0) return DWF_OK;
+        DhopCall c{in, out, nullptr, out_parity, dagger, EPI_EXTERIOR, 1.0, 0.0, PI, PI};
+        c.dd_cut = d->cut;
+        c.row_list = d->brows;
+        c.nrows_list = d->nbrows;
+        c.recv = d->recv;
+        c.seg_off = d->seg_off;
+        return launch_dhop(d->ctx, c, d->row_shape, st);
+    }
     if (stage == 0) {  // every face the neighbour domains need
         const long lanes = f.seg_off[kDdSegs] * f.Ls;
         const unsigned nb = (unsigned)((lanes + 255) / 256);
@@ -311,6 +342,7 @@ int dd_dhop(dwf_dd d, void *out, const void *in, int out_parity, int dagger, hip
     DWF_HIP(hipStreamWaitEvent(d->comm, d->ready, 0));
     if ((rc = dd_launch_any(d, nullptr, (const char *)in, out_parity, dagger, d->comm, 0))) return rc;
     DWF_HIP(hipMemcpyAsync(d->recv, d->send, d->face_bytes, hipMemcpyDeviceToDevice, d->comm));
+    if ((rc = dd_launch_any(d, (char *)out, (const char *)in, out_parity, dagger, d->comm, 2))) return rc;
     if ((rc = dd_launch_any(d, (char *)out, (const char *)in, out_parity, dagger, d->comm, 1))) return rc;
     DWF_HIP(hipEventRecord(d->halo, d->comm));
     // interior on the caller's stream, overlapping the faces and the exchange

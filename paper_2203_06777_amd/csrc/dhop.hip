@@ -181,6 +181,9 @@ static int launch_t(const DhopArgs &a, int ls_t, long nblocks, int threads, hipS
         DWF_HIP(hipGetLastError());
         return DWF_OK;
     }
+    if constexpr (EPI == EPI_EXTERIOR) {
+        return fail(DWF_EUNSUP, "hopping kernel: the exterior launch needs the row kernel");
+    } else {
     const size_t shm = EPI == EPI_M5INV ? (size_t)a.spb * a.Ls * 25 * sizeof(A) : 0;
     switch (ls_t) {
         case 8: hipLaunchKernelGGL((k_dhop<PI, PO, DAG, EPI, 8>), grid, block, shm, st, a); break;
@@ -190,17 +193,22 @@ static int launch_t(const DhopArgs &a, int ls_t, long nblocks, int threads, hipS
     }
     DWF_HIP(hipGetLastError());
     return DWF_OK;
+    }
 }
 
 template <int PI, int PO>
 static int launch_pp(const DhopArgs &a, int ls_t, int dagger, int epi, long nb, int th, hipStream_t st) {
-    if (epi == EPI_INTERIOR) {
-        // the interior of a decomposed apply: same storage in and out
+    if (epi == EPI_INTERIOR || epi == EPI_EXTERIOR) {
+        // the interior or the boundary rows of a decomposed apply: same storage in and out
         if constexpr (PI == PO) {
+            if (epi == EPI_EXTERIOR) {
+                if (dagger) return launch_t<PI, PO, 1, EPI_EXTERIOR>(a, ls_t, nb, th, st);
+                return launch_t<PI, PO, 0, EPI_EXTERIOR>(a, ls_t, nb, th, st);
+            }
             if (dagger) return launch_t<PI, PO, 1, EPI_INTERIOR>(a, ls_t, nb, th, st);
             return launch_t<PI, PO, 0, EPI_INTERIOR>(a, ls_t, nb, th, st);
         }
-        return fail(DWF_EUNSUP, "hopping kernel: the interior launch needs equal input and output precision");
+        return fail(DWF_EUNSUP, "hopping kernel: a decomposed launch needs equal input and output precision");
     }
     if (epi == EPI_CG) {
         // the solver's residual update: adjoint kernel, r in FP32 or FP64
@@ -277,8 +285,17 @@ int launch_dhop(dwf_ctx ctx, const DhopCall &c, const DhopShape &shape_in, hipSt
     a.cg_live = c.cg_live;
     if (c.schur_coef) m5inv_setup(g, a.m5i, true);
     if (c.links) a.links = (const char *)c.links;
-    a.dd_cut = c.epi == EPI_INTERIOR ? c.dd_cut : 0u;
+    a.dd_cut = (c.epi == EPI_INTERIOR || c.epi == EPI_EXTERIOR) ? c.dd_cut : 0u;
     a.stop = c.stop;
+    if (c.epi == EPI_EXTERIOR) {
+        if (!rows_mode || !c.row_list || !c.recv || !c.seg_off)
+            return fail(DWF_EINVAL, "hopping kernel: the exterior launch needs the row kernel, a row list and faces");
+        a.row_list = c.row_list;
+        a.nrows = (unsigned)c.nrows_list;
+        a.recv = (const char *)c.recv;
+        for (int k = 0; k < 9; ++k) a.seg_off[k] = c.seg_off[k];
+        if (c.nrows_list == 0) return DWF_OK;
+    }
     if (c.epi == EPI_CG && (!c.norm_out || !c.cg_alpha || !c.cg_live || !c.z))
         return fail(DWF_EINVAL, "hopping kernel: CG epilogue needs z, partials and the solver scalars");
     int threads;

@@ -88,6 +88,8 @@ enum Epi {
                     // written) -= (*cg_alpha) * y when *cg_live != 0, with |r|^2 partials in norm_out
     EPI_INTERIOR = 5,  // as EPI_SCALE, for the interior of a decomposed apply: output sites with a hop
                        // across a cut (DhopCall::dd_cut) are not written (same input and output precision)
+    EPI_EXTERIOR = 6,  // as EPI_SCALE over the rows listed in DhopCall::row_list (row kernel only): a hop
+                       // across a cut takes its half spinor from the received faces (DhopCall::recv)
 };
 
 struct DhopCall {
@@ -106,6 +108,10 @@ struct DhopCall {
     const void *links = nullptr; // gathered link table to use instead of the context's (same layout)
     unsigned dd_cut = 0;         // EPI_INTERIOR: cut directions, bit mu (x = 1, y = 2, z = 4, t = 8)
     const double *stop = nullptr;  // device flag: when nonzero at launch the kernel does nothing
+    const unsigned *row_list = nullptr;  // EPI_EXTERIOR: rows (y + L1 (z + L2 t)) to compute, nrows_list of them
+    long nrows_list = 0;
+    const void *recv = nullptr;          // EPI_EXTERIOR: received faces, segment 2 mu + side from seg_off[]
+    const long *seg_off = nullptr;       //   (kDdSegs + 1 prefix sums of face sites)
 };
 
 // Solver workspace (allocated on first solve).

@@ -37,9 +37,23 @@ struct DhopArgs {
     double *norm_out;
     const double *cg_alpha, *cg_live;
     M5InvCoef m5i;  // EPI_M5INV: Mooee^-1 (or the Moebius Schur factor)
-    unsigned dd_cut;  // EPI_INTERIOR: cut directions (bit mu)
+    unsigned dd_cut;  // EPI_INTERIOR, EPI_EXTERIOR: cut directions (bit mu)
     const double *stop;  // when non-null and *stop != 0 the launch does nothing (a solver that has stopped)
+    const unsigned *row_list;  // EPI_EXTERIOR: physical rows y + L1 (z + L2 t), nrows of them
+    const char *recv;          // EPI_EXTERIOR: received faces (half spinors, 12 reals of the arithmetic type)
+    long seg_off[9];           // EPI_EXTERIOR: first face site of segment 2 mu + side, prefix sums
 };
+
+// Face site index, within its segment, of the input site reached from output site (xh; x1, x2,
+// x3) across cut mu: faces are ordered like the lattice with mu removed; the x faces hold one
+// site per row pair, indexed by (y / 2, z, t).
+__device__ __forceinline__ long dd_face_index(int mu, unsigned xh, unsigned x1, unsigned x2, unsigned x3,
+                                              unsigned L0h, unsigned L1, unsigned L2) {
+    if (mu == 0) return (long)(x1 >> 1) + (long)(L1 / 2) * ((long)x2 + (long)L2 * x3);
+    if (mu == 1) return (long)xh + (long)L0h * ((long)x2 + (long)L2 * x3);
+    if (mu == 2) return (long)xh + (long)L0h * ((long)x1 + (long)L1 * x3);
+    return (long)xh + (long)L0h * ((long)x1 + (long)L1 * x2);
+}
 
 // Whether an output site has a hop across a cut of a domain decomposition: its coordinate
 // along a cut direction mu is 0 (backward hop) or L_mu - 1 (forward hop).
@@ -147,6 +161,20 @@ __device__ __forceinline__ void rowmap(const DhopArgs &a, unsigned q, unsigned &
     x3 = Tt * a.tt + lt;
 }
 
+// Coordinates of logical row q: the traversal order, or the listed row (EPI_EXTERIOR).
+template <int EPI>
+__device__ __forceinline__ void row_coords(const DhopArgs &a, unsigned q, unsigned &x1, unsigned &x2, unsigned &x3) {
+    if constexpr (EPI == EPI_EXTERIOR) {
+        const unsigned r = a.row_list[q];
+        const unsigned r2 = fdiv(r, a.lat.L1, a.lat.inv1);
+        x1 = r - r2 * a.lat.L1;
+        x3 = fdiv(r2, a.lat.L2, a.lat.inv2);
+        x2 = r2 - x3 * a.lat.L2;
+    } else {
+        rowmap(a, q, x1, x2, x3);
+    }
+}
+
 // Row block starting at logical row q0 (see the file comment); every lane of
 // the workgroup calls it.  smem holds row_lds_bytes(rows, L0h, Ls, PI) bytes
 // (and threads * 25 reals for EPI_M5INV).
@@ -170,14 +198,14 @@ __device__ __forceinline__ void row_block(const DhopArgs &a, unsigned q0, const 
     // lane coordinates and neighbour rows
     const bool active = t < nthr && q0 + r < a.nrows;
     unsigned x1 = 0, x2 = 0, x3 = 0;
-    if (active) rowmap(a, q0 + r, x1, x2, x3);
+    if (active) row_coords<EPI>(a, q0 + r, x1, x2, x3);
     if constexpr (EPI == EPI_INTERIOR) {
         // a block whose rows all lie on a y, z or t cut has no interior site: the whole workgroup leaves
         bool any = false;
         const unsigned nr = min((unsigned)a.rows, a.nrows - q0);
         for (unsigned rr = 0; rr < nr && !any; ++rr) {
             unsigned y1, y2, y3;
-            rowmap(a, q0 + rr, y1, y2, y3);
+            row_coords<EPI>(a, q0 + rr, y1, y2, y3);
             any = !dd_boundary(a.dd_cut & 14u, 1, y1, y2, y3, 4, a.lat.L1, a.lat.L2, a.lat.L3);
         }
         if (!any) return;
@@ -222,7 +250,7 @@ __device__ __forceinline__ void row_block(const DhopArgs &a, unsigned q0, const 
         const bool stager = t < nthr;
         {  // first row of the block: its staging loads, the neighbour loads, then the LDS writes
             unsigned y1, y2, y3;  // uniform across the workgroup
-            rowmap(a, q0, y1, y2, y3);
+            row_coords<EPI>(a, q0, y1, y2, y3);
             const size_t prow = y1 + a.lat.L1 * (y2 + a.lat.L2 * y3);
             const u32x4 *gl = (const u32x4 *)links_g + prow * VL;
             const u32x4 *gx = (const u32x4 *)in_f + prow * VX;
@@ -251,7 +279,7 @@ __device__ __forceinline__ void row_block(const DhopArgs &a, unsigned q0, const 
         }
         for (int rr = 1; rr < nrow_here && stager; ++rr) {
             unsigned y1, y2, y3;
-            rowmap(a, q0 + rr, y1, y2, y3);
+            row_coords<EPI>(a, q0 + rr, y1, y2, y3);
             const size_t prow = y1 + a.lat.L1 * (y2 + a.lat.L2 * y3);
             const u32x4 *gl = (const u32x4 *)links_g + prow * VL;
             const u32x4 *gx = (const u32x4 *)in_f + prow * VX;
@@ -261,7 +289,7 @@ __device__ __forceinline__ void row_block(const DhopArgs &a, unsigned q0, const 
     } else {
         for (int rr = 0; rr < nrow_here && t < nthr; ++rr) {
             unsigned y1, y2, y3;  // uniform across the workgroup
-            rowmap(a, q0 + rr, y1, y2, y3);
+            row_coords<EPI>(a, q0 + rr, y1, y2, y3);
             const size_t prow = y1 + a.lat.L1 * (y2 + a.lat.L2 * y3);
             const u32x4 *gl = (const u32x4 *)links_g + prow * VL;
             const u32x4 *gx = (const u32x4 *)in_f + prow * VX;
@@ -291,52 +319,75 @@ __device__ __forceinline__ void row_block(const DhopArgs &a, unsigned q0, const 
         const char *lk = reinterpret_cast<const char *>(lds_l) + (size_t)(r * L0h + xh) * 8 * 18 * PT<PI>::RB;
         const u32x4 *xr = lds_x + r * VX;
         constexpr int SG = DAG ? 1 : -1;
-#define DWF_HOP_LDS(DIR, MU, TAU, LX)                                                        \
+        // EPI_EXTERIOR: a hop that crosses a cut (FWD: from coordinate L - 1, else from 0) takes the
+        // received half spinor of face segment 2 mu + (FWD ? 0 : 1); the other instantiations drop
+        // this test at compile time.
+#define DWF_CROSS(MU, FWD, XC, LM) (EPI == EPI_EXTERIOR && ((a.dd_cut >> (MU)) & 1u) && ((FWD) ? (XC) + 1 == (LM) : (XC) == 0))
+#define DWF_FACE(MU, FWD)                                                                    \
+    {                                                                                        \
+        const unsigned fi_ = ((unsigned)a.seg_off[2 * (MU) + ((FWD) ? 0 : 1)] +              \
+                              (unsigned)dd_face_index(MU, (unsigned)xh, x1, x2, x3, (unsigned)L0h, L1, L2)) * \
+                                 (unsigned)Ls + (unsigned)s;                                 \
+        const u32x4 *src_ = reinterpret_cast<const u32x4 *>(a.recv) + fi_ * (unsigned)(12 * sizeof(A) / 16); \
+        u32x4 hv_[12 * sizeof(A) / 16];                                                      \
+        _Pragma("unroll") for (int k = 0; k < (int)(12 * sizeof(A) / 16); ++k) hv_[k] = src_[k]; \
+        __builtin_memcpy(h, hv_, sizeof(hv_));                                               \
+    }
+#define DWF_HOP_LDS(DIR, MU, TAU, LX, FWD)                                                   \
     {                                                                                        \
         A w[18], h[12];                                                                      \
-        u32x4 v[NG];                                                                         \
         load_link<PI>(lk, 0, DIR, w);                                                        \
-        _Pragma("unroll") for (int g = 0; g < NG; ++g) v[g] = xr[((LX)*NG + g) * Ls + s];    \
-        project_vecs<PI, MU, TAU>(v, h);                                                     \
+        if (DWF_CROSS(MU, FWD, x0, L0)) DWF_FACE(MU, FWD)                                    \
+        else {                                                                               \
+            u32x4 v[NG];                                                                     \
+            _Pragma("unroll") for (int g = 0; g < NG; ++g) v[g] = xr[((LX)*NG + g) * Ls + s];\
+            project_vecs<PI, MU, TAU>(v, h);                                                 \
+        }                                                                                    \
         mul_reconstruct<MU, TAU>(w, h, acc);                                                 \
     }
-#define DWF_HOP_GLB(DIR, MU, TAU, NB)                                                        \
+#define DWF_HOP_GLB(DIR, MU, TAU, NB, FWD, XC, LM)                                           \
     {                                                                                        \
         A w[18], h[12];                                                                      \
-        u32x4 v[NG];                                                                         \
         load_link<PI>(lk, 0, DIR, w);                                                        \
-        const Off off_ = spinor_off<PI, Off>(NB, Ls, s);                                     \
-        _Pragma("unroll") for (int g = 0; g < NG; ++g) v[g] =                                \
-            *(const u32x4 *)(in_f + off_ + (Off)(g * Ls * 16));                              \
-        project_vecs<PI, MU, TAU>(v, h);                                                     \
+        if (DWF_CROSS(MU, FWD, XC, LM)) DWF_FACE(MU, FWD)                                    \
+        else {                                                                               \
+            u32x4 v[NG];                                                                     \
+            const Off off_ = spinor_off<PI, Off>(NB, Ls, s);                                 \
+            _Pragma("unroll") for (int g = 0; g < NG; ++g) v[g] =                            \
+                *(const u32x4 *)(in_f + off_ + (Off)(g * Ls * 16));                          \
+            project_vecs<PI, MU, TAU>(v, h);                                                 \
+        }                                                                                    \
         mul_reconstruct<MU, TAU>(w, h, acc);                                                 \
     }
-#define DWF_HOP_REG(DIR, MU, TAU, K)                                                         \
+#define DWF_HOP_REG(DIR, MU, TAU, K, FWD, XC, LM)                                            \
     {                                                                                        \
         A w[18], h[12];                                                                      \
         load_link<PI>(lk, 0, DIR, w);                                                        \
-        project_vecs<PI, MU, TAU>(nbv[K], h);                                                \
+        if (DWF_CROSS(MU, FWD, XC, LM)) DWF_FACE(MU, FWD)                                    \
+        else project_vecs<PI, MU, TAU>(nbv[K], h);                                           \
         mul_reconstruct<MU, TAU>(w, h, acc);                                                 \
     }
         if constexpr (kPrefetch) {
-            DWF_HOP_LDS(0, 0, SG, lx0)
-            DWF_HOP_REG(1, 1, SG, 0)
-            DWF_HOP_REG(2, 2, SG, 1)
-            DWF_HOP_REG(3, 3, SG, 2)
-            DWF_HOP_LDS(4, 0, -SG, lx4)
-            DWF_HOP_REG(5, 1, -SG, 3)
-            DWF_HOP_REG(6, 2, -SG, 4)
-            DWF_HOP_REG(7, 3, -SG, 5)
+            DWF_HOP_LDS(0, 0, SG, lx0, true)
+            DWF_HOP_REG(1, 1, SG, 0, true, x1, L1)
+            DWF_HOP_REG(2, 2, SG, 1, true, x2, L2)
+            DWF_HOP_REG(3, 3, SG, 2, true, x3, L3)
+            DWF_HOP_LDS(4, 0, -SG, lx4, false)
+            DWF_HOP_REG(5, 1, -SG, 3, false, x1, L1)
+            DWF_HOP_REG(6, 2, -SG, 4, false, x2, L2)
+            DWF_HOP_REG(7, 3, -SG, 5, false, x3, L3)
         } else {
-            DWF_HOP_LDS(0, 0, SG, lx0)
-            DWF_HOP_GLB(1, 1, SG, nb1)
-            DWF_HOP_GLB(2, 2, SG, nb2)
-            DWF_HOP_GLB(3, 3, SG, nb3)
-            DWF_HOP_LDS(4, 0, -SG, lx4)
-            DWF_HOP_GLB(5, 1, -SG, nb5)
-            DWF_HOP_GLB(6, 2, -SG, nb6)
-            DWF_HOP_GLB(7, 3, -SG, nb7)
+            DWF_HOP_LDS(0, 0, SG, lx0, true)
+            DWF_HOP_GLB(1, 1, SG, nb1, true, x1, L1)
+            DWF_HOP_GLB(2, 2, SG, nb2, true, x2, L2)
+            DWF_HOP_GLB(3, 3, SG, nb3, true, x3, L3)
+            DWF_HOP_LDS(4, 0, -SG, lx4, false)
+            DWF_HOP_GLB(5, 1, -SG, nb5, false, x1, L1)
+            DWF_HOP_GLB(6, 2, -SG, nb6, false, x2, L2)
+            DWF_HOP_GLB(7, 3, -SG, nb7, false, x3, L3)
         }
+#undef DWF_CROSS
+#undef DWF_FACE
 #undef DWF_HOP_REG
 #undef DWF_HOP_LDS
 #undef DWF_HOP_GLB
@@ -344,7 +395,7 @@ __device__ __forceinline__ void row_block(const DhopArgs &a, unsigned q0, const 
 
     const A alpha = (A)a.alpha;
     const Off zoff = spinor_off<PI, Off>(c, Ls, s);
-    if constexpr (EPI == EPI_SCALE || EPI == EPI_INTERIOR) {
+    if constexpr (EPI == EPI_SCALE || EPI == EPI_INTERIOR || EPI == EPI_EXTERIOR) {
         if (!active) return;
         if (EPI == EPI_INTERIOR && dd_boundary(a.dd_cut, x0, x1, x2, x3, L0, L1, L2, L3)) return;
 #pragma unroll
