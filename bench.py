@@ -41,6 +41,20 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def probe_lib():
+    """The measurement probes (libdwf_probe.so, built in-tree by __graft_entry__.build())."""
+    import ctypes
+
+    path = os.path.join(ROOT, "paper_2203_06777_amd", "libdwf_probe.so")
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    P, U, I = ctypes.c_void_p, ctypes.c_uint, ctypes.c_int
+    lib.probe_stream_rows.argtypes = [P, P, P, U, U, U, P]
+    lib.probe_link_mult.argtypes = [P, P, P, I, I, I, P]
+    return lib
+
+
 def dhop_flops(vol, ls, nrhs=1):
     return 1320.0 * ls * (vol // 2) * nrhs
 
@@ -175,6 +189,27 @@ def main():
     copy_gbs = 2 * nbytes / (copy_ms * 1e-3) / 1e9
     log(f"copy 1 GiB -> 1 GiB: {copy_ms * 1e3:.1f} us, {copy_gbs:.0f} GB/s (read+write)")
     del src, dst
+    torch.cuda.empty_cache()
+
+    # ---------------- the apply's compulsory traffic alone (achievable-bandwidth reference) ----------------
+    probe = probe_lib()
+    nrows = vol // dims[0]
+    vx, vl = (dims[0] // 2) * ls * 96 // 16, (dims[0] // 2) * 8 * 18 * 4 // 16  # 16-byte vectors per row
+    s_in = torch.empty(nrows * vx * 16, dtype=torch.uint8, device="cuda").fill_(3)
+    s_out = torch.empty_like(s_in)
+    s_lk = torch.empty(nrows * vl * 16, dtype=torch.uint8, device="cuda").fill_(5)
+    cstream = torch.cuda.current_stream().cuda_stream
+
+    def stream_apply():
+        rc = probe.probe_stream_rows(s_out.data_ptr(), s_in.data_ptr(), s_lk.data_ptr(), nrows, vx, vl, cstream)
+        assert rc == 0, rc
+
+    for _ in range(3):
+        stream_apply()
+    stream_ms = timed(stream_apply, 20)
+    stream_gbs = algo_bytes / (stream_ms * 1e-3) / 1e9
+    log(f"compulsory-traffic stream of one apply: {stream_ms * 1e3:.1f} us, {stream_gbs:.0f} GB/s")
+    del s_in, s_out, s_lk
     torch.cuda.empty_cache()
 
     # ---------------- a1: Dhop in the other precisions ----------------
@@ -511,6 +546,36 @@ def main():
             log(f"row hmc: {rh}")
         op4.close()
 
+    # ---------------- the link multiply on the vector ALUs and on the matrix cores ----------------
+    if row_on("link_mult_probe"):
+        rng2 = np.random.default_rng(7)
+        u3 = F.gauge_field((2, 2, 2, 2), 0.5, 11)[0, 0, 0, 0, 0]  # one SU(3) matrix
+        m6 = np.block([[u3.real, -u3.imag], [u3.imag, u3.real]]).astype(np.float32)  # real form, orthogonal
+        mat = torch.from_numpy(m6.ravel().copy()).cuda()
+        nwg, reps = 4096, 256
+        ncol = {0: nwg * 256, 1: nwg * 64, 2: nwg * 64}
+        cols = torch.from_numpy(rng2.standard_normal(nwg * 256 * 6).astype(np.float32)).cuda()
+        res = {}
+        for mode, nm in ((0, "valu"), (1, "mfma_operands_in_place"), (2, "mfma_with_lane_shuffles")):
+            out_t = torch.empty(ncol[mode] * 6, dtype=torch.float32, device="cuda")
+            cst = torch.cuda.current_stream().cuda_stream
+
+            def go(r):
+                assert probe.probe_link_mult(out_t.data_ptr(), mat.data_ptr(), cols.data_ptr(), mode, nwg, r, cst) == 0
+
+            go(1)  # one product: checked against the CPU
+            torch.cuda.synchronize()
+            xc = cols[: ncol[mode] * 6].cpu().numpy().reshape(-1, 6).astype(np.float64)
+            ref = xc @ m6.astype(np.float64).T
+            err = float(np.abs(out_t.cpu().numpy().reshape(-1, 6) - ref).max() / np.abs(ref).max())
+            ms = timed(lambda: go(reps), 5)
+            tf = ncol[mode] * reps * 72 / (ms * 1e-3) / 1e12
+            res[nm] = {"useful_tflops": round(tf, 1), "one_product_max_rel_err": err}
+        res["note"] = ("(6x6 real) x (6 x N) link multiply, operands in registers, " f"{nwg} workgroups x {reps} "
+                       "rounds; useful flops 72 per column; MFMA = v_mfma_f32_16x16x4f32 on a 16x8 padded matrix")
+        rows["link_mult_probe"] = res
+        log(f"row link_mult_probe: {res}")
+
     # ---------------- software-managed device cache: host fields beyond a device budget ----------------
     if row_on("cache_16^4x16_f32"):
         w = F.WORKLOADS["dhop_16^4x16"]
@@ -591,6 +656,9 @@ def main():
         "parity_rel_l2_sampled": parity_err,
         "copy_gbs": round(copy_gbs, 1),
         "frac_of_copy": round(achieved / copy_gbs, 4),
+        # a kernel that moves exactly the apply's compulsory bytes in the same row shape, no arithmetic
+        "stream_gbs": round(stream_gbs, 1),
+        "frac_of_stream": round(achieved / stream_gbs, 4),
         "cpu_baseline": cpu,
         # the paper's own figures, on other hardware and an unstated workload: context, not the target
         "paper_context": {"dwf_tflops_per_gpu": 1.3, "hardware": "AMD MI100 (early HIP port)",

@@ -1,4 +1,4 @@
-"""Build libdwf.so (HIP, gfx950) in-tree from csrc/*.hip.
+"""Build libdwf.so (HIP, gfx950) in-tree from csrc/*.hip, and the benchmark's probes.
 
 Every translation unit is compiled with hipcc for gfx950 only; packed FP32
 instructions are disabled (-packed-fp32-ops) and the objects are linked into
@@ -37,8 +37,25 @@ def _compile(src: str) -> str:
     return obj
 
 
+PROBE_SRC = os.path.join(HERE, "probe", "probe.hip")
+PROBE_LIB = os.path.join(HERE, "libdwf_probe.so")
+
+
+def build_probe(verbose: bool = False) -> str:
+    """Compile the benchmark's measurement probes (probe/probe.hip) into libdwf_probe.so."""
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [HIPCC, *CFLAGS, "-shared", PROBE_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {PROBE_SRC}:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PROBE_LIB)
+    if verbose:
+        print(f"built {PROBE_LIB}")
+    return PROBE_LIB
+
+
 def build(jobs: int = 8, verbose: bool = False) -> str:
-    """Compile every csrc/*.hip and link libdwf.so; always rebuilds."""
+    """Compile every csrc/*.hip and link libdwf.so (and the probes); always rebuilds."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
@@ -51,6 +68,7 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB}")
+    build_probe(verbose)
     return LIB
 
 
