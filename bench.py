@@ -52,6 +52,8 @@ def probe_lib():
     P, U, I = ctypes.c_void_p, ctypes.c_uint, ctypes.c_int
     lib.probe_stream_rows.argtypes = [P, P, P, U, U, U, P]
     lib.probe_link_mult.argtypes = [P, P, P, I, I, I, P]
+    lib.probe_dhop_pattern.argtypes = [P, P, P, U, U, U, U, I, I, P]
+    lib.probe_read.argtypes = [P, P, ctypes.c_size_t, P]
     return lib
 
 
@@ -211,6 +213,33 @@ def main():
     log(f"compulsory-traffic stream of one apply: {stream_ms * 1e3:.1f} us, {stream_gbs:.0f} GB/s")
     del s_in, s_out, s_lk
     torch.cuda.empty_cache()
+
+    # ---------------- the kernel's memory accesses alone, and re-read bandwidth by footprint ----------------
+    if row_on("memory_pattern_32^4x16") and dims == (32, 32, 32, 32) and ls == 16:
+        ty_, tz_, tt_ = 8, 4, 32  # the default traversal tile at this shape
+        p_in = torch.empty(nrows * vx * 16, dtype=torch.uint8, device="cuda").fill_(3)
+        p_out = torch.empty_like(p_in)
+        p_lk = torch.empty(nrows * vl * 16, dtype=torch.uint8, device="cuda").fill_(5)
+        pat = {}
+        for nbr, sto, nm in ((1, 1, "all_accesses"), (0, 1, "no_neighbour_reads"), (1, 0, "no_output_stores")):
+            def go():
+                assert probe.probe_dhop_pattern(p_out.data_ptr(), p_in.data_ptr(), p_lk.data_ptr(), 32, ty_, tz_, tt_,
+                                                nbr, sto, cstream) == 0
+            go()
+            pat[nm + "_us"] = round(timed(go, 10) * 1e3, 1)
+        reads = {}
+        sink = torch.empty(16, dtype=torch.uint8, device="cuda")
+        for mb in (16, 64, 128, 256, 768):
+            nv = mb * (1 << 20) // 16
+            t_ms = timed(lambda: probe.probe_read(p_in.data_ptr(), sink.data_ptr(), nv, cstream), 10)
+            reads[f"{mb}MB_tbs"] = round(mb * (1 << 20) / (t_ms * 1e-3) / 1e12, 2)
+        pat["reread_bandwidth_by_footprint"] = reads
+        pat["note"] = ("the row kernel's reads and writes at this shape with no arithmetic (probe_dhop_pattern, tile "
+                       f"{ty_}x{tz_}x{tt_}); reread: a grid-stride read of the first N MB over and over")
+        rows["memory_pattern_32^4x16"] = pat
+        log(f"row memory_pattern: {pat}")
+        del p_in, p_out, p_lk
+        torch.cuda.empty_cache()
 
     # ---------------- a1: Dhop in the other precisions ----------------
     def dhop_row(prec, rb):

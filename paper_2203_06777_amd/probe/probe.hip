@@ -4,6 +4,13 @@
 //   kernel's shape and nothing else: workgroup q reads one links block (vl 16-byte vectors) and
 //   one input row (vx vectors) and writes one output row (vx vectors, non-temporal stores).  Its
 //   time is the bandwidth a kernel moving exactly those bytes reaches on this chip.
+// probe_dhop_pattern: the memory accesses of the FP32 row kernel at L^3 rows of 256 lanes (L0h = 16,
+//   Ls = 16) and nothing else: same XCD remap and (ty, tz, tt) row order, the links block and the
+//   own row read once per workgroup, each lane's six y/z/t neighbour spinors (6 vectors each) read
+//   (or, with neighbours = 0, not), the output row written with non-temporal stores (or, with
+//   stores = 0, not); the values only feed an xor.
+// probe_read: reads n 16-byte vectors over and over with a grid-stride loop (footprints that fit
+//   the L2, the Infinity Cache or neither).
 // probe_link_mult: the SU(3) link multiply as a (6 x 6 real) x (6 x N real) product, three ways:
 //   mode 0  vector ALU: lane j holds column j (6 reals) and multiplies it by the matrix (36 FMAs);
 //   mode 1  matrix cores, operands already in the MFMA layout: A = the matrix padded to 16 x 8,
@@ -30,6 +37,63 @@ __global__ void __launch_bounds__(256) k_stream_rows(u32x4 *__restrict__ out, co
         w.x ^= m.x ^ m.y ^ m.z ^ m.w;
         __builtin_nontemporal_store(w, O + v);
     }
+}
+
+__device__ inline unsigned xcd_block(unsigned b, unsigned nb) {  // consecutive blocks per XCD
+    const unsigned q = nb / 8, r = nb % 8, x = b % 8, k = b / 8;
+    return x * q + (x < r ? x : r) + k;
+}
+
+template <int NBR, int STORE>
+__global__ void __launch_bounds__(256) k_dhop_pattern(u32x4 *__restrict__ out, const u32x4 *__restrict__ in,
+                                                      const u32x4 *__restrict__ lk, unsigned L, unsigned ty,
+                                                      unsigned tz, unsigned tt) {
+    const unsigned q = xcd_block(blockIdx.x, gridDim.x);
+    const unsigned per = ty * tz * tt;
+    const unsigned T = q / per, w = q % per;
+    const unsigned ly = w % ty, lz = (w / ty) % tz, lt = w / (ty * tz);
+    const unsigned ntt = L / tt, nty = L / ty;
+    const unsigned Tt = T % ntt, Ty = (T / ntt) % nty, Tz = T / (ntt * nty);
+    const unsigned y = Ty * ty + ly, z = Tz * tz + lz, t3 = Tt * tt + lt;
+    const unsigned row = y + L * (z + L * t3);
+    const int t = threadIdx.x, xh = t >> 4, s = t & 15;
+    constexpr unsigned VX = 1536, VL = 576;  // 16-byte vectors per row: input (16 sites x 16 s x 96 B), links
+    const u32x4 *Lr = lk + (size_t)row * VL;
+    const u32x4 *I = in + (size_t)row * VX;
+    u32x4 acc = Lr[t] ^ Lr[256 + t];
+    if (t < 64) acc ^= Lr[512 + t];
+#pragma unroll
+    for (int u = 0; u < 6; ++u) acc ^= I[u * 256 + t];
+    if (NBR) {
+        const unsigned nb[6] = {((y + 1) % L) + L * (z + L * t3), y + L * (((z + 1) % L) + L * t3),
+                                y + L * (z + L * ((t3 + 1) % L)), ((y + L - 1) % L) + L * (z + L * t3),
+                                y + L * (((z + L - 1) % L) + L * t3), y + L * (z + L * ((t3 + L - 1) % L))};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const u32x4 *N = in + (size_t)nb[k] * VX + xh * 96 + s;
+#pragma unroll
+            for (int g = 0; g < 6; ++g) acc ^= N[g * 16];
+        }
+    }
+    u32x4 *O = out + (size_t)row * VX;
+    if (STORE) {
+#pragma unroll
+        for (int u = 0; u < 6; ++u) {
+            u32x4 v = acc;
+            v.x += u;
+            __builtin_nontemporal_store(v, O + u * 256 + t);
+        }
+    } else if (acc.x == 0x9e3779b9u && acc.y == 0x7f4a7c15u) {
+        O[t] = acc;  // keeps the loads; practically never taken
+    }
+}
+
+__global__ void k_read(const u32x4 *__restrict__ in, u32x4 *sink, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t st = (size_t)gridDim.x * blockDim.x;
+    u32x4 acc = {0, 0, 0, 0};
+    for (; i < n; i += st) acc ^= in[i];
+    if (acc.x == 0x12345678u && acc.y == 0x9abcdef0u) sink[0] = acc;
 }
 
 // mat: 36 floats (row-major 6 x 6), the same for every wave; cols: per wave 64 columns of 6 floats
@@ -117,6 +181,27 @@ int probe_stream_rows(void *out, const void *in, const void *links, unsigned nro
     if (!out || !in || !links || nrows == 0) return -1;
     hipLaunchKernelGGL(k_stream_rows, dim3(nrows), dim3(256), 0, (hipStream_t)stream, (u32x4 *)out,
                        (const u32x4 *)in, (const u32x4 *)links, vx, vl);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// L^3 rows; in and out hold L^3 * 1536 vectors, links L^3 * 576; ty, tz, tt divide L.
+int probe_dhop_pattern(void *out, const void *in, const void *links, unsigned L, unsigned ty, unsigned tz, unsigned tt,
+                       int neighbours, int stores, void *stream) {
+    if (!out || !in || !links || L == 0 || !ty || !tz || !tt || L % ty || L % tz || L % tt) return -1;
+    const hipStream_t st = (hipStream_t)stream;
+    const unsigned nrows = L * L * L;
+    u32x4 *o = (u32x4 *)out;
+    const u32x4 *i = (const u32x4 *)in, *l = (const u32x4 *)links;
+    if (neighbours && stores) hipLaunchKernelGGL((k_dhop_pattern<1, 1>), dim3(nrows), dim3(256), 0, st, o, i, l, L, ty, tz, tt);
+    else if (neighbours) hipLaunchKernelGGL((k_dhop_pattern<1, 0>), dim3(nrows), dim3(256), 0, st, o, i, l, L, ty, tz, tt);
+    else if (stores) hipLaunchKernelGGL((k_dhop_pattern<0, 1>), dim3(nrows), dim3(256), 0, st, o, i, l, L, ty, tz, tt);
+    else hipLaunchKernelGGL((k_dhop_pattern<0, 0>), dim3(nrows), dim3(256), 0, st, o, i, l, L, ty, tz, tt);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int probe_read(const void *in, void *sink, size_t nvec, void *stream) {
+    if (!in || !sink || nvec == 0) return -1;
+    hipLaunchKernelGGL(k_read, dim3(8192), dim3(256), 0, (hipStream_t)stream, (const u32x4 *)in, (u32x4 *)sink, nvec);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
