@@ -58,11 +58,27 @@ struct dwf_cache_s {
 namespace dwf {
 namespace {
 
+// Makes the cache's device current for the scope of a call (device backend), restoring the
+// caller's device after.
+struct OnDevice {
+    int prev = -1;
+    explicit OnDevice(dwf_cache c) {
+        if (c->backend == DWF_CACHE_DEVICE && hipGetDevice(&prev) == hipSuccess && prev != c->device)
+            (void)hipSetDevice(c->device);
+        else
+            prev = -1;
+    }
+    ~OnDevice() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
 int dev_alloc(dwf_cache c, void **p, size_t bytes) {
     if (c->backend == DWF_CACHE_HOST_SIM) {
         *p = std::aligned_alloc(256, (bytes + 255) & ~(size_t)255);
         return *p ? DWF_OK : fail(DWF_ENOMEM, "dwf_cache: host stand-in allocation failed");
     }
+    OnDevice on(c);
     if (hipMalloc(p, bytes) != hipSuccess) {
         *p = nullptr;
         return fail(DWF_ENOMEM, "dwf_cache: hipMalloc failed below the watermark");
@@ -71,8 +87,12 @@ int dev_alloc(dwf_cache c, void **p, size_t bytes) {
 }
 
 void dev_free(dwf_cache c, void *p) {
-    if (c->backend == DWF_CACHE_HOST_SIM) std::free(p);
-    else (void)hipFree(p);
+    if (c->backend == DWF_CACHE_HOST_SIM) {
+        std::free(p);
+        return;
+    }
+    OnDevice on(c);
+    (void)hipFree(p);
 }
 
 // to_host: device -> host.  Copies are ordered on `st`; sync waits for them.
@@ -208,6 +228,7 @@ int dwf_cache_open(dwf_cache c, void *host, size_t bytes, int intent, void **vie
         if (!e->dev) {
             if ((rc = make_resident(c, e, st))) return rc;
             e->pos = c->lru[e->advice].insert(c->lru[e->advice].begin(), e);
+            e->state = DWF_ST_CPU_DIRTY;  // the new device copy is stale until the copy below lands
             if ((rc = copy(c, e, false, st))) return rc;
             e->state = DWF_ST_CONSISTENT;
         } else {
@@ -269,7 +290,7 @@ int dwf_cache_release(dwf_cache c, void *host, void *stream) {
     int rc;
     if (e->dev) {
         if ((rc = evict(c, e, st))) return rc;
-        c->st.evictions -= 1;  // a release is not an eviction
+        c->st.evictions -= 1;  // counted as a release, not as an eviction
     }
     if ((rc = sync(c, st))) return rc;
     c->table.erase(it);
