@@ -197,8 +197,9 @@ int dwf_axpy(dwf_ctx ctx, void *y, double a_re, double a_im, const void *x, int 
 int dwf_cg(dwf_ctx ctx, void *x, const void *b, double tol, int maxit, int mode, dwf_cg_stats *stats,
            void *stream);
 
-/* Inner-solve controls of modes 1-3: relative residual target of each inner
- * solve and its iteration cap (<= 0 restores the defaults 1e-2 and 2000). */
+/* Inner-solve controls of modes 1-3: relative residual reduction of each inner
+ * solve (the last one stops where the outer tolerance needs) and its iteration cap
+ * (<= 0 restores the defaults: 1e-4 for mode 1, 1e-2 for modes 2 and 3; 2000). */
 int dwf_cg_set_inner(dwf_ctx ctx, double inner_tol, int inner_maxit);
 
 /* Solves D_DW x = b (dagger = 0) or D_DW^dag x = b (dagger = 1) on full FP64

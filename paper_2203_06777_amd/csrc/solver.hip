@@ -129,6 +129,33 @@ __global__ void __launch_bounds__(256) k_convert_scale(u32x4 *out, const u32x4 *
     store_spinor<PO>(out, c, Ls, s, v);
 }
 
+// The FP64 residual refresh of the FP32 inner iteration (a reliable update): with r the
+// recursive FP32 residual and p the direction the last iteration built from it (old scaling),
+// r' = scale * r64 is the true residual in the new scaling and the direction is rebuilt from it,
+//   p' = r' + c (p - r),   c = (|r_true|^2 / |r|^2) (scale / old scale),
+// i.e. p - r = beta p_prev (the previous direction) carried over with the beta of the true residual.
+__global__ void __launch_bounds__(256) k_refresh_f32(u32x4 *r, u32x4 *p, const u32x4 *r64, double scale, double c,
+                                                     long nrows, int Ls) {
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= nrows * Ls) return;
+    const long row = t / Ls;
+    const int s = (int)(t - row * Ls);
+    double rt[24];
+    float rv[24], pv[24];
+    load_spinor<DWF_F64>(r64, row, Ls, s, rt);
+    load_spinor<DWF_F32>(r, row, Ls, s, rv);
+    load_spinor<DWF_F32>(p, row, Ls, s, pv);
+    const float cf = (float)c;
+#pragma unroll
+    for (int k = 0; k < 24; ++k) {
+        const float rn = (float)(scale * rt[k]);
+        pv[k] = rn + cf * (pv[k] - rv[k]);
+        rv[k] = rn;
+    }
+    store_spinor<DWF_F32>(r, row, Ls, s, rv);
+    store_spinor<DWF_F32>(p, row, Ls, s, pv);
+}
+
 // y (FP64) += a * x (FP32).
 __global__ void __launch_bounds__(256) k_axpy_f32_to_f64(u32x4 *y, const u32x4 *x, double a, long nrows, int Ls) {
     const long t = (long)blockIdx.x * 256 + threadIdx.x;
@@ -241,7 +268,7 @@ static int norm2_sync(dwf_ctx ctx, const void *x, int prec, double *out, hipStre
 // the caller left in place.  vprec is the precision of x and r (F64 or F32);
 // oprec the operator's, which p is stored in.
 static int cg_core(dwf_ctx ctx, int vprec, int oprec, void *x, void *r, void *p, double stop_rr, int budget,
-                   bool keep_p, int *iters_out, int *status_out, hipStream_t st) {
+                   bool keep_p, int *iters_out, int *status_out, hipStream_t st, double *rr_out = nullptr) {
     const Geom &g = ctx->g;
     const long n = g.half * g.Ls * 12;
     const unsigned nb = nb256(g.half * g.Ls);
@@ -290,6 +317,7 @@ static int cg_core(dwf_ctx ctx, int vprec, int oprec, void *x, void *r, void *p,
     DWF_HIP(hipMemcpy(hs, scal, 8 * sizeof(double), hipMemcpyDeviceToHost));
     *iters_out = (int)hs[S_ITERS];
     *status_out = (int)hs[S_DONE];
+    if (rr_out) *rr_out = hs[S_RR];
     return DWF_OK;
 }
 
@@ -317,16 +345,18 @@ int cg_solve(dwf_ctx ctx, void *x, const void *b, double tol, int maxit, int mod
         return finish(DWF_OK);
     }
     const int oprec = mode == 1 ? DWF_F32 : mode == 2 ? DWF_F16 : DWF_BF16;
-    // Each inner solve gains two digits, then the residual is recomputed in FP64.  With the
-    // FP32 operator the iteration goes on from it with the search direction it had (a
-    // reliable update: the Krylov space is kept, 160 against 165 iterations of restarted
-    // inner solves on the 24^4 x 12 workload, where FP64 CG takes 158); a 16-bit direction
-    // carries too much rounding to be kept (172 against 165 iterations), so those restart
-    // from p = r.
-    double inner_tol = ctx->inner_tol > 0 ? ctx->inner_tol : 1e-2;
+    // Each inner solve gains a few digits, then the residual is recomputed in FP64.  With the
+    // FP32 operator the iteration goes on from it (a reliable update): the true residual
+    // replaces the recursive one and the search direction is rebuilt from it with the
+    // previous direction carried over, so the Krylov space is kept; a 16-bit direction
+    // carries too much rounding to be kept (172 against 165 iterations on the 24^4 x 12
+    // workload), so those restart from p = r.
+    // Defaults: FP32 inner solves gain four digits (three FP64 refreshes to 1e-10), 16-bit ones two
+    // (their operator's rounding limits what one inner solve can win).
+    double inner_tol = ctx->inner_tol > 0 ? ctx->inner_tol : (mode == 1 ? 1e-4 : 1e-2);
     int inner_maxit = ctx->inner_maxit > 0 ? ctx->inner_maxit : 2000;
     int total = 0;
-    double rr = 0, prev_scale = 0, xx = 0;
+    double rr = 0, prev_scale = 0, xx = 0, rec_rr = 0;  // rec_rr: the last inner solve's recursive |r|^2
     if ((rc = norm2_sync(ctx, x, DWF_F64, &xx, st))) return rc;
     bool x_zero = xx == 0.0;  // a zero start needs no operator application for its residual
     for (;;) {
@@ -359,27 +389,25 @@ int cg_solve(dwf_ctx ctx, void *x, const void *b, double tol, int maxit, int mod
             // inner solve A e = r^, r^ = r * sqrt(n)/|r| in FP32 (components of order one)
             const double scale = std::sqrt((double)n) / std::sqrt(rr);
             const unsigned nbv = nb256(g.half * g.Ls);
-            hipLaunchKernelGGL((k_convert_scale<DWF_F64, DWF_F32>), nbv, 256, 0, st, (u32x4 *)w.r32,
-                               (const u32x4 *)w.r64, scale, g.half, g.Ls);
+            void *p = oprec == DWF_F32 ? w.p32 : w.p16;
+            const bool keep_p = oprec == DWF_F32 && prev_scale > 0 && rec_rr > 0;
+            if (keep_p) {  // reliable update: true residual in the new scaling, direction rebuilt from it
+                const double c = (prev_scale / scale) * (double)n / rec_rr;
+                hipLaunchKernelGGL(k_refresh_f32, nbv, 256, 0, st, (u32x4 *)w.r32, (u32x4 *)p, (const u32x4 *)w.r64,
+                                   scale, c, g.half, g.Ls);
+            } else {
+                hipLaunchKernelGGL((k_convert_scale<DWF_F64, DWF_F32>), nbv, 256, 0, st, (u32x4 *)w.r32,
+                                   (const u32x4 *)w.r64, scale, g.half, g.Ls);
+            }
+            DWF_HIP(hipGetLastError());
             DWF_HIP(hipMemsetAsync(w.e32, 0, cb_bytes(g, DWF_F32), st));
             const int budget = std::min(inner_maxit, maxit - total);
-            void *p = oprec == DWF_F32 ? w.p32 : w.p16;
-            const bool keep_p = oprec == DWF_F32 && prev_scale > 0;
-            if (keep_p) {  // the kept direction into the new scaling of the system
-                u32x4 *p4 = (u32x4 *)p;
-                const double f = scale / prev_scale;
-                if (oprec == DWF_F32)
-                    hipLaunchKernelGGL((k_convert_scale<DWF_F32, DWF_F32>), nbv, 256, 0, st, p4, p4, f, g.half, g.Ls);
-                else if (oprec == DWF_F16)
-                    hipLaunchKernelGGL((k_convert_scale<DWF_F16, DWF_F16>), nbv, 256, 0, st, p4, p4, f, g.half, g.Ls);
-                else
-                    hipLaunchKernelGGL((k_convert_scale<DWF_BF16, DWF_BF16>), nbv, 256, 0, st, p4, p4, f, g.half,
-                                       g.Ls);
-                DWF_HIP(hipGetLastError());
-            }
             prev_scale = scale;
-            if ((rc = cg_core(ctx, DWF_F32, oprec, w.e32, w.r32, p, inner_tol * inner_tol * (double)n, budget, keep_p,
-                              &it, &status, st)))
+            // relative reduction of this inner solve: inner_tol, but no further than the outer
+            // tolerance needs (with a factor 2 of margin for the FP64 residual it is checked on)
+            const double want = std::max(inner_tol, 0.5 * tol * std::sqrt(bb / rr));
+            if ((rc = cg_core(ctx, DWF_F32, oprec, w.e32, w.r32, p, want * want * (double)n, budget, keep_p, &it,
+                              &status, st, &rec_rr)))
                 return rc;
             hipLaunchKernelGGL(k_axpy_f32_to_f64, nb256(g.half * g.Ls), 256, 0, st, (u32x4 *)x,
                                (const u32x4 *)w.e32, 1.0 / scale, g.half, g.Ls);
