@@ -12,7 +12,10 @@
 //             site and s in the arithmetic type.  The x faces live in the halved-x checkerboard
 //             layout: the slice x = 0 of one parity holds site xh = 0 of every other row.
 //   exchange  one device copy of the send buffer into the receive buffer (the stand-in for the
-//             peer transfers: every face comes back to this domain).
+//             peer transfers: every face comes back to this domain).  FP32 / FP64 receive into
+//             ghost sites of the field layout: the half spinor lands in a site's upper spin pair,
+//             the lower pair stays zero, so the projection of the crossing hop returns it as it
+//             was sent and the hopping kernel reads a crossing neighbour like any other site.
 //   interior  the hopping kernel writing only the output sites with no hop across a cut (a
 //             workgroup whose rows all lie on a y, z or t cut leaves at once), on the caller's
 //             stream, overlapping the faces and the exchange on the plan's stream.
@@ -20,7 +23,10 @@
 //             cut from the received half spinors and the rest from the local input, and written
 //             (no read-modify-write of the output): the rows on a y, z or t cut by the row-block
 //             kernel (EPI_EXTERIOR: its links and x-rows staged in LDS like every row launch),
-//             the remaining x-cut sites by a kernel with one lane per (site, s).
+//             the remaining x-cut sites by a kernel with one lane per (site, s).  With the x
+//             direction cut, FP32 / FP64 compute every row in the exterior kernel instead (each
+//             row holds one x-boundary site; its crossing neighbour comes from an LDS slot), and
+//             there is no interior launch.
 //
 // Every hop runs through the same projection and link multiply as dwf_dhop, in the same order,
 // so the decomposed apply equals dwf_dhop bit for bit.
@@ -107,12 +113,23 @@ __global__ void __launch_bounds__(256) k_dd_faces(typename PT<PI>::A *send, cons
         case 6: project_vecs<PI, 3, SG>(v, h); break;
         default: project_vecs<PI, 3, -SG>(v, h); break;
     }
-    A *dst = send + t * 12;
+    if constexpr (PI == DWF_F32 || PI == DWF_F64) {
+        // the upper spin pair of a field-layout site: the exchange drops it into the ghost sites
+        constexpr int NH = NG / 2;
+        u32x4 hv[NH];
+        __builtin_memcpy(hv, h, sizeof(hv));
+        u32x4 *dst = reinterpret_cast<u32x4 *>(send) + (site * NH) * f.Ls + s;
 #pragma unroll
-    for (int k = 0; k < 12; ++k) dst[k] = h[k];
+        for (int g = 0; g < NH; ++g) dst[(long)g * f.Ls] = hv[g];
+    } else {
+        A *dst = send + t * 12;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) dst[k] = h[k];
+    }
 }
 
-// Listed boundary sites: the whole stencil, hops across a cut from the received faces.
+// Listed boundary sites: the whole stencil, hops across a cut from the received faces (FP32 /
+// FP64: recv is the ghost buffer, the half spinor in the upper spin pair of each site).
 template <int PI, int DAG>
 __global__ void __launch_bounds__(256) k_dd_exterior(char *out, const char *in, const char *links,
                                                      const typename PT<PI>::A *recv, const unsigned *blist, long nb,
@@ -142,8 +159,16 @@ __global__ void __launch_bounds__(256) k_dd_exterior(char *out, const char *in, 
         load_link<PI>(links, c, DIR, w);                                                               \
         if (cross) {                                                                                   \
             const int seg = 2 * MU + (FWD ? 0 : 1);                                                    \
-            const A *src = recv + ((f.seg_off[seg] + face_index(f, MU, xh, x1, x2, x3)) * f.Ls + s) * 12; \
-            _Pragma("unroll") for (int k = 0; k < 12; ++k) h[k] = src[k];                             \
+            const long fi = f.seg_off[seg] + face_index(f, MU, xh, x1, x2, x3);                        \
+            if constexpr (PI == DWF_F32 || PI == DWF_F64) { /* upper pair of the ghost site */       \
+                u32x4 hv[NG / 2];                                                                      \
+                const u32x4 *src = reinterpret_cast<const u32x4 *>(recv) + (fi * NG) * f.Ls + s;       \
+                _Pragma("unroll") for (int g = 0; g < NG / 2; ++g) hv[g] = src[(long)g * f.Ls];        \
+                __builtin_memcpy(h, hv, sizeof(hv));                                                   \
+            } else {                                                                                   \
+                const A *src = recv + (fi * f.Ls + s) * 12;                                            \
+                _Pragma("unroll") for (int k = 0; k < 12; ++k) h[k] = src[k];                         \
+            }                                                                                          \
         } else {                                                                                       \
             long nbr;                                                                                  \
             if (MU == 0) {                                                                             \
@@ -180,13 +205,16 @@ struct dwf_dd_s {
     int prec = 0;
     unsigned cut = 0;
     long seg_off[dwf::kDdSegs + 1] = {};
-    void *send = nullptr, *recv = nullptr;  // all faces, concatenated by segment
+    void *send = nullptr, *recv = nullptr;  // all faces, concatenated by segment (16-bit storage: recv)
+    void *ghost = nullptr;  // FP32 / FP64: the received faces as field-layout sites (upper spin pair =
+                            // half spinor, lower pair zero from creation on); the exchange fills the upper pairs
     size_t face_bytes = 0;
     unsigned *blist[2] = {};  // boundary output sites left to the site kernel, per output parity
     long nb[2] = {};
     unsigned *brows = nullptr;  // rows on a y, z or t cut (computed by the row kernel)
     long nbrows = 0;
     dwf::DhopShape row_shape;   // launch shape of the exterior rows
+    bool all_rows = false;      // every row is an exterior row (FP32 / FP64 with the x direction cut)
     hipStream_t comm = nullptr;
     hipEvent_t ready = nullptr, halo = nullptr;
 };
@@ -198,6 +226,7 @@ int dd_destroy(dwf_dd d) {
     (void)hipDeviceSynchronize();
     (void)hipFree(d->send);
     (void)hipFree(d->recv);
+    (void)hipFree(d->ghost);
     for (unsigned *p : d->blist) (void)hipFree(p);
     (void)hipFree(d->brows);
     if (d->comm) (void)hipStreamDestroy(d->comm);
@@ -225,22 +254,46 @@ int dd_create(dwf_ctx ctx, int prec, unsigned cut, dwf_dd *out) {
         d->seg_off[seg + 1] = d->seg_off[seg] + (((cut >> mu) & 1u) ? g.half / g.L[mu] : 0);
     }
     const size_t areal = prec == DWF_F64 ? 8 : 4;
+    const bool wide = prec == DWF_F32 || prec == DWF_F64;
     d->face_bytes = (size_t)d->seg_off[kDdSegs] * g.Ls * 12 * areal;
-    if (hipMalloc(&d->send, d->face_bytes) != hipSuccess || hipMalloc(&d->recv, d->face_bytes) != hipSuccess)
+    if (hipMalloc(&d->send, d->face_bytes) != hipSuccess)
         return bail(DWF_ENOMEM, "dwf_dd_create: hipMalloc of the face buffers failed");
+    if (wide) {
+        if (hipMalloc(&d->ghost, 2 * d->face_bytes) != hipSuccess)
+            return bail(DWF_ENOMEM, "dwf_dd_create: hipMalloc of the ghost sites failed");
+        if (hipMemset(d->ghost, 0, 2 * d->face_bytes) != hipSuccess)
+            return bail(DWF_EHIP, "dwf_dd_create: clearing the ghost sites failed");
+    } else if (hipMalloc(&d->recv, d->face_bytes) != hipSuccess) {
+        return bail(DWF_ENOMEM, "dwf_dd_create: hipMalloc of the face buffers failed");
+    }
     // the exterior: rows on a y, z or t cut go to the row kernel when it applies to this lattice,
     // the other boundary sites (x cut) to the site kernel
     const unsigned L0 = g.L[0], L1 = g.L[1], L2 = g.L[2], L3 = g.L[3], L0h = L0 / 2;
     d->row_shape = ctx->shape[prec][0].rows > 0 ? ctx->shape[prec][0] : default_row_shape(g, prec, ctx->lds_limit);
-    const bool by_rows = d->row_shape.rows > 0 && row_shape_ok(g, d->row_shape, prec, ctx->lds_limit);
+    if (wide) d->row_shape.rows = 1;  // the FP32 / FP64 exterior kernel takes one row per workgroup
+    const bool by_rows = d->row_shape.rows > 0 && row_shape_ok(g, d->row_shape, prec, ctx->lds_limit) &&
+                         (!wide || row_lds_bytes(1, (int)L0h, g.Ls, prec) + (size_t)g.Ls * 24 * areal <= ctx->lds_limit);
     auto row_cut = [&](unsigned x1, unsigned x2, unsigned x3) {
         return ((cut & 2u) && (x1 == 0 || x1 + 1 == L1)) || ((cut & 4u) && (x2 == 0 || x2 + 1 == L2)) ||
                ((cut & 8u) && (x3 == 0 || x3 + 1 == L3));
     };
+    // With the x direction cut every x-row holds a boundary site (the row's first or last site,
+    // by parity); FP32 / FP64 then compute every row after the exchange in the exterior kernel (the
+    // crossing x-hop from an LDS slot) instead of splitting each row between the interior launch and
+    // a site kernel, which re-reads eight scattered neighbours per boundary site.
+    d->all_rows = wide && by_rows && (cut & 1u);
     if (by_rows) {
+        // the rows in the traversal order of the plain apply (tiles of the launch shape), so the
+        // workgroups in flight on one XCD share their neighbour rows as they do there
+        const unsigned ty = (unsigned)d->row_shape.ty, tz = (unsigned)d->row_shape.tz, tt = (unsigned)d->row_shape.tt;
+        const unsigned per = ty * tz * tt, nty = L1 / ty, ntt = L3 / tt;
         std::vector<unsigned> rows;
-        for (unsigned r = 0; r < L1 * L2 * L3; ++r)
-            if (row_cut(r % L1, (r / L1) % L2, r / (L1 * L2))) rows.push_back(r);
+        for (unsigned q = 0; q < L1 * L2 * L3; ++q) {
+            const unsigned T = q / per, w = q % per, ly = w % ty, lz = (w / ty) % tz, lt = w / ty / tz;
+            const unsigned Tt = T % ntt, Ty = (T / ntt) % nty, Tz = T / ntt / nty;
+            const unsigned x1 = Ty * ty + ly, x2 = Tz * tz + lz, x3 = Tt * tt + lt;
+            if (d->all_rows || row_cut(x1, x2, x3)) rows.push_back(x1 + L1 * (x2 + L2 * x3));
+        }
         d->nbrows = (long)rows.size();
         if (hipMalloc(&d->brows, std::max<size_t>(1, rows.size()) * sizeof(unsigned)) != hipSuccess)
             return bail(DWF_ENOMEM, "dwf_dd_create: hipMalloc of the boundary rows failed");
@@ -257,7 +310,7 @@ int dd_create(dwf_ctx ctx, int prec, unsigned cut, dwf_dd *out) {
                            x3 = (unsigned)(rest / ((long)L1 * L2));
             const unsigned x0 = 2 * xh + ((p + x1 + x2 + x3) & 1u);
             const bool on_row = row_cut(x1, x2, x3);
-            if (by_rows && on_row) continue;
+            if (d->all_rows || (by_rows && on_row)) continue;
             if (on_row || ((cut & 1u) && (x0 == 0 || x0 + 1 == L0))) list.push_back((unsigned)c);
         }
         d->nb[p] = (long)list.size();
@@ -300,6 +353,7 @@ static int dd_launch(dwf_dd d, char *out, const char *in, int out_parity, int da
         c.row_list = d->brows;
         c.nrows_list = d->nbrows;
         c.recv = d->recv;
+        c.ghost = d->ghost;
         c.seg_off = d->seg_off;
         return launch_dhop(d->ctx, c, d->row_shape, st);
     }
@@ -313,11 +367,12 @@ static int dd_launch(dwf_dd d, char *out, const char *in, int out_parity, int da
         if (n == 0) return DWF_OK;
         const unsigned nb = (unsigned)((n * f.Ls + 255) / 256);
         const char *lk = (const char *)d->ctx->links[PI][out_parity];
+        const A *faces = (const A *)(d->ghost ? d->ghost : d->recv);
         if (dagger)
-            hipLaunchKernelGGL((k_dd_exterior<PI, 1>), nb, 256, 0, st, out, in, lk, (const A *)d->recv,
+            hipLaunchKernelGGL((k_dd_exterior<PI, 1>), nb, 256, 0, st, out, in, lk, faces,
                                d->blist[out_parity], n, f);
         else
-            hipLaunchKernelGGL((k_dd_exterior<PI, 0>), nb, 256, 0, st, out, in, lk, (const A *)d->recv,
+            hipLaunchKernelGGL((k_dd_exterior<PI, 0>), nb, 256, 0, st, out, in, lk, faces,
                                d->blist[out_parity], n, f);
     }
     DWF_HIP(hipGetLastError());
@@ -333,6 +388,16 @@ static int dd_launch_any(dwf_dd d, char *out, const char *in, int out_parity, in
     }
 }
 
+// The stand-in for the peer transfers: every face comes back to this domain.  FP32 / FP64: into the
+// upper spin pair of the ghost sites (one strided copy: rows of a site's half-spinor vectors).
+static hipError_t dd_exchange(dwf_dd d, hipStream_t st) {
+    if (!d->ghost) return hipMemcpyAsync(d->recv, d->send, d->face_bytes, hipMemcpyDeviceToDevice, st);
+    const size_t nsites = (size_t)d->seg_off[kDdSegs];
+    if (nsites == 0) return hipSuccess;
+    const size_t half = d->face_bytes / nsites;  // one site's half spinors, all s
+    return hipMemcpy2DAsync(d->ghost, 2 * half, d->send, half, half, nsites, hipMemcpyDeviceToDevice, st);
+}
+
 int dd_dhop(dwf_dd d, void *out, const void *in, int out_parity, int dagger, hipStream_t st) {
     dwf_ctx ctx = d->ctx;
     if (!ctx->gauge_set) return fail(DWF_EUNSUP, "dwf_dd_dhop: gauge not set");
@@ -341,14 +406,16 @@ int dd_dhop(dwf_dd d, void *out, const void *in, int out_parity, int dagger, hip
     DWF_HIP(hipEventRecord(d->ready, st));
     DWF_HIP(hipStreamWaitEvent(d->comm, d->ready, 0));
     if ((rc = dd_launch_any(d, nullptr, (const char *)in, out_parity, dagger, d->comm, 0))) return rc;
-    DWF_HIP(hipMemcpyAsync(d->recv, d->send, d->face_bytes, hipMemcpyDeviceToDevice, d->comm));
+    DWF_HIP(dd_exchange(d, d->comm));
     if ((rc = dd_launch_any(d, (char *)out, (const char *)in, out_parity, dagger, d->comm, 2))) return rc;
     if ((rc = dd_launch_any(d, (char *)out, (const char *)in, out_parity, dagger, d->comm, 1))) return rc;
     DWF_HIP(hipEventRecord(d->halo, d->comm));
     // interior on the caller's stream, overlapping the faces and the exchange
-    DhopCall c{in, out, nullptr, out_parity, dagger, EPI_INTERIOR, 1.0, 0.0, d->prec, d->prec};
-    c.dd_cut = d->cut;
-    if ((rc = launch_dhop(ctx, c, ctx->shape[d->prec][dagger], st))) return rc;
+    if (!d->all_rows) {
+        DhopCall c{in, out, nullptr, out_parity, dagger, EPI_INTERIOR, 1.0, 0.0, d->prec, d->prec};
+        c.dd_cut = d->cut;
+        if ((rc = launch_dhop(ctx, c, ctx->shape[d->prec][dagger], st))) return rc;
+    }
     DWF_HIP(hipStreamWaitEvent(st, d->halo, 0));
     return DWF_OK;
 }

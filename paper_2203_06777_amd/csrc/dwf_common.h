@@ -110,7 +110,8 @@ struct DhopCall {
     const double *stop = nullptr;  // device flag: when nonzero at launch the kernel does nothing
     const unsigned *row_list = nullptr;  // EPI_EXTERIOR: rows (y + L1 (z + L2 t)) to compute, nrows_list of them
     long nrows_list = 0;
-    const void *recv = nullptr;          // EPI_EXTERIOR: received faces, segment 2 mu + side from seg_off[]
+    const void *recv = nullptr;          // EPI_EXTERIOR, 16-bit storage: received faces, segment 2 mu + side from seg_off[]
+    const void *ghost = nullptr;         // EPI_EXTERIOR, FP32 / FP64: received faces as field-layout sites
     const long *seg_off = nullptr;       //   (kDdSegs + 1 prefix sums of face sites)
 };
 

@@ -40,7 +40,10 @@ struct DhopArgs {
     unsigned dd_cut;  // EPI_INTERIOR, EPI_EXTERIOR: cut directions (bit mu)
     const double *stop;  // when non-null and *stop != 0 the launch does nothing (a solver that has stopped)
     const unsigned *row_list;  // EPI_EXTERIOR: physical rows y + L1 (z + L2 t), nrows of them
-    const char *recv;          // EPI_EXTERIOR: received faces (half spinors, 12 reals of the arithmetic type)
+    const char *recv;          // EPI_EXTERIOR, 16-bit storage: received faces (half spinors, 12 reals of the
+                               //   arithmetic type, one (face site, s) after the other)
+    const char *ghost;         // EPI_EXTERIOR, FP32 / FP64: received faces as spinor sites of the field layout
+                               //   (upper spin pair = the half spinor, lower pair = 0), site seg_off[seg] + face index
     long seg_off[9];           // EPI_EXTERIOR: first face site of segment 2 mu + side, prefix sums
 };
 
@@ -190,7 +193,10 @@ __device__ __forceinline__ void row_block(const DhopArgs &a, unsigned q0, const 
     const int per_row = L0h * Ls;
     const int nthr = a.rows * per_row;
     const int t = threadIdx.x;
-    const int r = t / per_row;
+    // FP32 / FP64 exterior: one row per workgroup (the host launches it so), so the row coordinates,
+    // and with them every y, z and t cut test, are uniform across the workgroup
+    constexpr bool kGhost = EPI == EPI_EXTERIOR && (PI == DWF_F32 || PI == DWF_F64);
+    const int r = kGhost ? 0 : t / per_row;
     const int wi = t - r * per_row;
     const int xh = wi / Ls;
     const int s = wi - xh * Ls;
@@ -198,7 +204,8 @@ __device__ __forceinline__ void row_block(const DhopArgs &a, unsigned q0, const 
     // lane coordinates and neighbour rows
     const bool active = t < nthr && q0 + r < a.nrows;
     unsigned x1 = 0, x2 = 0, x3 = 0;
-    if (active) row_coords<EPI>(a, q0 + r, x1, x2, x3);
+    if (kGhost) row_coords<EPI>(a, q0, x1, x2, x3);
+    else if (active) row_coords<EPI>(a, q0 + r, x1, x2, x3);
     if constexpr (EPI == EPI_INTERIOR) {
         // a block whose rows all lie on a y, z or t cut has no interior site: the whole workgroup leaves
         bool any = false;
@@ -310,6 +317,19 @@ __device__ __forceinline__ void row_block(const DhopArgs &a, unsigned q0, const 
             for (int v = t + kX * nthr; v < VX; v += nthr) dx[v] = gx[v];
         }
     }
+    if constexpr (kGhost) {
+        // x cut: the row's one site whose x-hop crosses (the last site hopping forward when the row
+        // starts at odd x, else the first hopping backward) reads its neighbour from an extra LDS
+        // slot after the x-row, filled here from the received face
+        if (a.dd_cut & 1u) {
+            const unsigned o = ((unsigned)a.parity + x1 + x2 + x3) & 1u;
+            const unsigned fi = (unsigned)a.seg_off[o ? 0 : 1] +
+                                (unsigned)dd_face_index(0, o ? (unsigned)L0h - 1u : 0u, x1, x2, x3, (unsigned)L0h,
+                                                        a.lat.L1, a.lat.L2);
+            const u32x4 *gs = reinterpret_cast<const u32x4 *>(a.ghost) + (size_t)fi * (size_t)(NG * Ls);
+            for (int v = t; v < NG * Ls; v += nthr) lds_x[VX + v] = gs[v];
+        }
+    }
     __syncthreads();
 
     A acc[24];
@@ -320,8 +340,10 @@ __device__ __forceinline__ void row_block(const DhopArgs &a, unsigned q0, const 
         const u32x4 *xr = lds_x + r * VX;
         constexpr int SG = DAG ? 1 : -1;
         // EPI_EXTERIOR: a hop that crosses a cut (FWD: from coordinate L - 1, else from 0) takes the
-        // received half spinor of face segment 2 mu + (FWD ? 0 : 1); the other instantiations drop
-        // this test at compile time.
+        // received half spinor of face segment 2 mu + (FWD ? 0 : 1): FP32 / FP64 read it as a field
+        // site (upper pair = half spinor, lower pair = 0, so the projection returns it unchanged) by
+        // a select of address, 16-bit storage (face in the wider arithmetic type) by a branch; the
+        // other instantiations drop this test at compile time.
 #define DWF_CROSS(MU, FWD, XC, LM) (EPI == EPI_EXTERIOR && ((a.dd_cut >> (MU)) & 1u) && ((FWD) ? (XC) + 1 == (LM) : (XC) == 0))
 #define DWF_FACE(MU, FWD)                                                                    \
     {                                                                                        \
@@ -337,7 +359,12 @@ __device__ __forceinline__ void row_block(const DhopArgs &a, unsigned q0, const 
     {                                                                                        \
         A w[18], h[12];                                                                      \
         load_link<PI>(lk, 0, DIR, w);                                                        \
-        if (DWF_CROSS(MU, FWD, x0, L0)) DWF_FACE(MU, FWD)                                    \
+        if constexpr (kGhost) {                                                              \
+            const int lx_ = DWF_CROSS(MU, FWD, x0, L0) ? L0h : (LX);                         \
+            u32x4 v[NG];                                                                     \
+            _Pragma("unroll") for (int g = 0; g < NG; ++g) v[g] = xr[(lx_ * NG + g) * Ls + s];\
+            project_vecs<PI, MU, TAU>(v, h);                                                 \
+        } else if (DWF_CROSS(MU, FWD, x0, L0)) DWF_FACE(MU, FWD)                             \
         else {                                                                               \
             u32x4 v[NG];                                                                     \
             _Pragma("unroll") for (int g = 0; g < NG; ++g) v[g] = xr[((LX)*NG + g) * Ls + s];\
@@ -349,7 +376,19 @@ __device__ __forceinline__ void row_block(const DhopArgs &a, unsigned q0, const 
     {                                                                                        \
         A w[18], h[12];                                                                      \
         load_link<PI>(lk, 0, DIR, w);                                                        \
-        if (DWF_CROSS(MU, FWD, XC, LM)) DWF_FACE(MU, FWD)                                    \
+        if constexpr (kGhost) {                                                              \
+            /* a crossing hop reads the received face site like a field site: no branch */   \
+            const bool cr_ = DWF_CROSS(MU, FWD, XC, LM);                                     \
+            const char *b_ = cr_ ? a.ghost : in_f;                                           \
+            const unsigned fr_ = (MU) == 1 ? x2 + L2 * x3 : ((MU) == 2 ? x1 + L1 * x3 : x1 + L1 * x2); \
+            const unsigned fb_ = (unsigned)a.seg_off[2 * (MU) + ((FWD) ? 0 : 1)] + (unsigned)L0h * fr_; \
+            const Off st_ = cr_ ? (Off)(fb_ + (unsigned)xh) : (Off)(NB);                      \
+            const Off off_ = spinor_off<PI, Off>(st_, Ls, s);                                \
+            u32x4 v[NG];                                                                     \
+            _Pragma("unroll") for (int g = 0; g < NG; ++g) v[g] =                            \
+                *(const u32x4 *)(b_ + off_ + (Off)(g * Ls * 16));                            \
+            project_vecs<PI, MU, TAU>(v, h);                                                 \
+        } else if (DWF_CROSS(MU, FWD, XC, LM)) DWF_FACE(MU, FWD)                             \
         else {                                                                               \
             u32x4 v[NG];                                                                     \
             const Off off_ = spinor_off<PI, Off>(NB, Ls, s);                                 \
