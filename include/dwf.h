@@ -247,17 +247,21 @@ int dwf_gauge_norm2(dwf_ctx ctx, double *result, const double *X, void *stream);
  * GPUs).  An output site is on the boundary when a hop crosses a cut.  dwf_dd_dhop runs, on
  * a stream of the plan, one face kernel (the half spinors, 6 complex per site and s in the
  * arithmetic type, of the input slices x_mu = 0 and x_mu = L_mu - 1 of every cut mu, with the
- * projector of the hop that crosses), one device copy standing in for the peer transfers, and
- * the boundary sites computed from the received faces; meanwhile the caller's stream runs the
- * hopping kernel on the interior sites only.  The result equals dwf_dhop bit for bit. */
+ * projector of the hop that crosses), one device copy standing in for the peer transfers (FP32 /
+ * FP64: into ghost sites of the field layout, the half spinor in the upper spin pair), and the
+ * boundary sites computed from the received faces; meanwhile the caller's stream runs the
+ * hopping kernel on the interior sites only.  FP32 / FP64 plans that cut x (every x-row then
+ * holds a boundary site) compute every row from the received faces after the exchange and have
+ * no interior launch.  The result equals dwf_dhop bit for bit. */
 #define DWF_CUT_X 1
 #define DWF_CUT_Y 2
 #define DWF_CUT_Z 4
 #define DWF_CUT_T 8
 
-/* Plan for precision prec and the cut mask `cuts` (1..15): allocates the send and receive
- * face buffers (2 x sum over cut mu of V/(2 L_mu) x Ls x 12 reals each), the boundary site
- * lists and a stream.  The plan reads the context's link tables at every apply (a gauge
+/* Plan for precision prec and the cut mask `cuts` (1..15): allocates the send face buffer
+ * (sum over cut mu of V/(2 L_mu) x Ls x 12 reals) and the receive side (the same size; FP32 /
+ * FP64: ghost sites of twice that size, cleared here), the boundary row and site lists and a
+ * stream.  The plan reads the context's link tables at every apply (a gauge
  * change needs no new plan); the context must outlive the plan. */
 int dwf_dd_create(dwf_ctx ctx, int prec, int cuts, dwf_dd *dd);
 /* out = D_h^{p<-1-p} in (dagger: D_h^dag) through the decomposition; the caller's stream
