@@ -176,7 +176,8 @@ int dwf_create(const dwf_geom *geom, dwf_ctx *out) {
     for (int k = 0; k < 2; ++k)
         if (hipEventCreateWithFlags((hipEvent_t *)&c->events[k], hipEventDisableTiming) != hipSuccess)
             return cleanup(DWF_EHIP, "dwf_create: hipEventCreate failed");
-    if (hipMemset(c->scal, 0, sizeof(double) * 16) != hipSuccess)
+    // cleared on the null stream, which a caller's non-blocking stream does not wait for
+    if (hipMemset(c->scal, 0, sizeof(double) * 16) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
         return cleanup(DWF_EHIP, "dwf_create: hipMemset failed");
     apply_tuned(c);
     *out = c;

@@ -324,6 +324,9 @@ int dd_create(dwf_ctx ctx, int prec, unsigned cut, dwf_dd *out) {
         hipEventCreateWithFlags(&d->ready, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&d->halo, hipEventDisableTiming) != hipSuccess)
         return bail(DWF_EHIP, "dwf_dd_create: stream or event creation failed");
+    // the clears and copies above ran on the null stream, which the plan's non-blocking stream and
+    // a caller's non-blocking stream do not wait for
+    if (hipDeviceSynchronize() != hipSuccess) return bail(DWF_EHIP, "dwf_dd_create: device synchronisation failed");
     *out = d;
     return DWF_OK;
 }
