@@ -680,6 +680,9 @@ def main():
                    "Ls": ls, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     # FETCH_SIZE counts every L2 fill from the fabric, Infinity-Cache hits included:
+                     # an upper bound on the HBM bytes
+                     "traffic_counts": "L2 fills (FETCH_SIZE) + L2 writes (WRITE_SIZE), calibrated on a 1 GiB copy",
                      "kernel": "k_dhop_rows<F32,F32,0,EPI_SCALE,16>", "algorithmic_bytes_per_launch": algo_bytes,
                      "us_per_launch": round(apply_ms * 1e3, 2), "kernel_src_sha": kernel_source_sha()},
         "parity_rel_l2_sampled": parity_err,
