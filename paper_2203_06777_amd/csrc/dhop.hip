@@ -188,8 +188,8 @@ static int launch_t(const DhopArgs &a, int ls_t, long nblocks, int threads, hipS
         DWF_HIP(hipGetLastError());
         return DWF_OK;
     }
-    if constexpr (EPI == EPI_EXTERIOR) {
-        return fail(DWF_EUNSUP, "hopping kernel: the exterior launch needs the row kernel");
+    if constexpr (EPI == EPI_EXTERIOR || EPI == EPI_INTERIOR_ROWS) {
+        return fail(DWF_EUNSUP, "hopping kernel: this decomposed launch needs the row kernel");
     } else {
     const size_t shm = EPI == EPI_M5INV ? (size_t)a.spb * a.Ls * 25 * sizeof(A) : 0;
     switch (ls_t) {
@@ -205,12 +205,16 @@ static int launch_t(const DhopArgs &a, int ls_t, long nblocks, int threads, hipS
 
 template <int PI, int PO>
 static int launch_pp(const DhopArgs &a, int ls_t, int dagger, int epi, long nb, int th, hipStream_t st) {
-    if (epi == EPI_INTERIOR || epi == EPI_EXTERIOR) {
+    if (epi == EPI_INTERIOR || epi == EPI_EXTERIOR || epi == EPI_INTERIOR_ROWS) {
         // the interior or the boundary rows of a decomposed apply: same storage in and out
         if constexpr (PI == PO) {
             if (epi == EPI_EXTERIOR) {
                 if (dagger) return launch_t<PI, PO, 1, EPI_EXTERIOR>(a, ls_t, nb, th, st);
                 return launch_t<PI, PO, 0, EPI_EXTERIOR>(a, ls_t, nb, th, st);
+            }
+            if (epi == EPI_INTERIOR_ROWS) {
+                if (dagger) return launch_t<PI, PO, 1, EPI_INTERIOR_ROWS>(a, ls_t, nb, th, st);
+                return launch_t<PI, PO, 0, EPI_INTERIOR_ROWS>(a, ls_t, nb, th, st);
             }
             if (dagger) return launch_t<PI, PO, 1, EPI_INTERIOR>(a, ls_t, nb, th, st);
             return launch_t<PI, PO, 0, EPI_INTERIOR>(a, ls_t, nb, th, st);
@@ -292,7 +296,7 @@ int launch_dhop(dwf_ctx ctx, const DhopCall &c, const DhopShape &shape_in, hipSt
     a.cg_live = c.cg_live;
     if (c.schur_coef) m5inv_setup(g, a.m5i, true);
     if (c.links) a.links = (const char *)c.links;
-    a.dd_cut = (c.epi == EPI_INTERIOR || c.epi == EPI_EXTERIOR) ? c.dd_cut : 0u;
+    a.dd_cut = (c.epi == EPI_INTERIOR || c.epi == EPI_EXTERIOR || c.epi == EPI_INTERIOR_ROWS) ? c.dd_cut : 0u;
     a.stop = c.stop;
     if (c.epi == EPI_EXTERIOR) {
         const bool wide = c.prec_in == DWF_F32 || c.prec_in == DWF_F64;
@@ -307,6 +311,8 @@ int launch_dhop(dwf_ctx ctx, const DhopCall &c, const DhopShape &shape_in, hipSt
         for (int k = 0; k < 9; ++k) a.seg_off[k] = c.seg_off[k];
         if (c.nrows_list == 0) return DWF_OK;
     }
+    if (c.epi == EPI_INTERIOR_ROWS && (!rows_mode || shape.rows != 1 || (c.dd_cut & 1u)))
+        return fail(DWF_EINVAL, "hopping kernel: the whole-row interior launch needs one row per workgroup and no x cut");
     if (c.epi == EPI_CG && (!c.norm_out || !c.cg_alpha || !c.cg_live || !c.z))
         return fail(DWF_EINVAL, "hopping kernel: CG epilogue needs z, partials and the solver scalars");
     int threads;

@@ -90,6 +90,9 @@ enum Epi {
                        // across a cut (DhopCall::dd_cut) are not written (same input and output precision)
     EPI_EXTERIOR = 6,  // as EPI_SCALE over the rows listed in DhopCall::row_list (row kernel only): a hop
                        // across a cut takes its half spinor from the received faces (DhopCall::recv)
+    EPI_INTERIOR_ROWS = 7,  // as EPI_INTERIOR when the boundary is whole rows (x not cut) and a workgroup
+                            // holds one row (row kernel only): a workgroup on a cut leaves, the others
+                            // store every site (no per-site test before the stores)
 };
 
 struct DhopCall {

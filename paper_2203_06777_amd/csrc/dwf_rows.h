@@ -206,7 +206,7 @@ __device__ __forceinline__ void row_block(const DhopArgs &a, unsigned q0, const 
     unsigned x1 = 0, x2 = 0, x3 = 0;
     if (kGhost) row_coords<EPI>(a, q0, x1, x2, x3);
     else if (active) row_coords<EPI>(a, q0 + r, x1, x2, x3);
-    if constexpr (EPI == EPI_INTERIOR) {
+    if constexpr (EPI == EPI_INTERIOR || EPI == EPI_INTERIOR_ROWS) {
         // a block whose rows all lie on a y, z or t cut has no interior site: the whole workgroup leaves
         bool any = false;
         const unsigned nr = min((unsigned)a.rows, a.nrows - q0);
@@ -434,7 +434,7 @@ __device__ __forceinline__ void row_block(const DhopArgs &a, unsigned q0, const 
 
     const A alpha = (A)a.alpha;
     const Off zoff = spinor_off<PI, Off>(c, Ls, s);
-    if constexpr (EPI == EPI_SCALE || EPI == EPI_INTERIOR || EPI == EPI_EXTERIOR) {
+    if constexpr (EPI == EPI_SCALE || EPI == EPI_INTERIOR || EPI == EPI_EXTERIOR || EPI == EPI_INTERIOR_ROWS) {
         if (!active) return;
         if (EPI == EPI_INTERIOR && dd_boundary(a.dd_cut, x0, x1, x2, x3, L0, L1, L2, L3)) return;
 #pragma unroll

@@ -94,6 +94,28 @@ def test_dd_rows_too_long_for_the_row_kernel(prec, cuts):
     op.close()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16", "bf16"])
+@pytest.mark.parametrize("cuts", ["t", "yz", "yzt"])
+def test_dd_whole_row_interior(prec, cuts):
+    """x-rows of 16 sites x Ls 16 (one row per workgroup) and no x cut: the interior launch that
+    stores every site of the rows it keeps."""
+    dims, ls = (32, 4, 2, 4), 16
+    op, u = make(dims, ls, seed_u=911)
+    dd = D().dwf_dd_create(op.handle, prec, cuts)
+    for par in (0, 1):
+        psi = F.fermion_cb(dims, ls, 912 + par)
+        pin = op.pack(to_dev(psi), 1 - par, prec)
+        for dag in (0, 1):
+            want, got = op.zeros(prec), op.zeros(prec)
+            D().dwf_dhop(op.handle, want, pin, par, dag, prec)
+            D().dwf_dd_dhop(dd, got, pin, par, dag)
+            torch.cuda.synchronize()
+            assert torch.equal(got, want), (prec, cuts, par, dag)
+            assert rel(op.unpack(got, par, prec).cpu().numpy(), R.dhop_cb(u, psi, par, bool(dag))) <= TOL[prec]
+    D().dwf_dd_destroy(dd)
+    op.close()
+
+
 def test_dd_repeated_calls_and_errors():
     dims, ls = (4, 4, 4, 4), 4
     op, u = make(dims, ls, seed_u=911)
